@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: compress + decompress throughput of a cosmology-like snapshot.
+
+Workload: 2^26 particles x 6 float32 fields (xx yy zz vx vy vz, 1.5 GiB),
+20k Poisson halos with Gaussian offsets plus a 30% uniform background in 8^3
+spatial-cell order, velocities = halo bulk + thermal; bound eb = 1e-4 x value
+range per field; best-fit LV / LCF / QCF predictor per 4096-value block;
+one canonical Huffman code per predictor.  Inputs are resident in HBM before
+timing starts.
+
+A step compresses the six fields in one batched launch sequence and
+decompresses them in another.  `value` is original bytes over the time of a
+step (compress + decompress).  The dominant kernel's HBM roofline fraction is
+its algorithmic bytes per launch over its average launch duration, measured
+with HIP events on the launch stream inside the timed region.  The CPU
+oracle is timed on a bounded sample of the same fields on one host core.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "compress+decompress GB/s and ratio at eb=1e-4·range vs oracle; % HBM peak"
+
+
+def algorithmic_bytes(kernel, n_total, comp_bytes):
+    """Bytes the method must move per launch of each kernel (see design notes)."""
+    return {
+        "k_range": 4 * n_total,               # read every value
+        "k_quant": 4 * n_total,               # read every value
+        "k_pack": 4 * n_total + comp_bytes,   # read every value, write the stream
+        "d_decode": comp_bytes + 4 * n_total,  # read the stream, write every value
+    }.get(kernel)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=1 << 26)
+    ap.add_argument("--eb", type=float, default=1e-4)
+    ap.add_argument("--block-log2", type=int, default=12)
+    ap.add_argument("--policy", default="bestfit", choices=["lv", "lcf", "bestfit"])
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19, help="values per field timed on the oracle")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              "(each GPU would compress its own particles independently)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1711_03888_amd import datagen, sznb
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.time()
+    snap = datagen.cosmology(args.particles, seed=2)
+    names = list(datagen.FIELD_NAMES)
+    print("generated %d particles in %.1fs" % (args.particles, time.time() - t_gen), file=sys.stderr, flush=True)
+    host = [snap[k] for k in names]
+    fields = [torch.from_numpy(h).to(dev) for h in host]
+    n = args.particles
+    n_total = n * len(fields)
+    pol = {"lv": sznb.PRED_LV, "lcf": sznb.PRED_LCF, "bestfit": sznb.PRED_BESTFIT}[args.policy]
+    mode = pol | sznb.EB_REL | sznb.BLOCK_LOG2(args.block_log2)
+    caps = [sznb.compress_bound(n, mode)] * len(fields)
+    outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    lens = torch.zeros(len(fields), dtype=torch.int64, device=dev)
+    ws_c = sznb.workspace(sznb.compress_workspace_bytes([n] * len(fields), [mode] * len(fields)), dev)
+    ws_d = sznb.workspace(sznb.decompress_workspace_bytes([n] * len(fields)), dev)
+    recon = [torch.empty(n, dtype=torch.float32, device=dev) for _ in fields]
+
+    def compress():
+        sznb.compress_batch_async(fields, args.eb, mode, caps=caps, ws=ws_c, outs=outs, lens=lens)
+
+    def decompress():
+        sznb.decompress_batch_async(outs, [n] * len(fields), outs=recon, ws=ws_d)
+
+    for _ in range(args.warmup):
+        compress()
+        decompress()
+    torch.cuda.synchronize()
+    first, st = sznb.read_status(ws_c, len(fields))
+    if first != sznb.OK:
+        raise SystemExit("compression failed: %s" % st)
+    first, st = sznb.read_status(ws_d, len(fields))
+    if first != sznb.OK:
+        raise SystemExit("decompression failed: %s" % st)
+
+    # timed region
+    sznb.profile(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        compress()
+        ev[i][1].record()
+        decompress()
+        ev[i][2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sznb.profile(False)
+    kern = sznb.profile_summary()
+    c_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / args.steps
+    d_ms = sum(b.elapsed_time(c) for _, b, c in ev) / args.steps
+    ms_step = wall * 1e3 / args.steps
+
+    # results of the last step
+    sizes = [int(v) for v in lens.cpu()]
+    comp_bytes = sum(sizes)
+    ratio = 4.0 * n_total / comp_bytes
+    worst = 0.0
+    for f, (x, y, s) in enumerate(zip(fields, recon, outs)):
+        eb_abs = sznb.stream_info(bytes(s[:128].cpu().numpy()))["eb_abs"]
+        err = (x.double() - y.double()).abs().max().item()
+        assert err <= eb_abs, (names[f], err, eb_abs)
+        worst = max(worst, err / eb_abs)
+
+    # roofline of the dominant kernel
+    dom = max((k for k in kern if algorithmic_bytes(k, n_total, comp_bytes)), key=lambda k: kern[k][0])
+    avg_ms = kern[dom][0] / kern[dom][1]
+    ach = algorithmic_bytes(dom, n_total, comp_bytes) / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(4.0 * n_total / (ms_step * 1e-3) / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cosmology snapshot, %d particles x 6 float32 fields (halos + background, "
+                               "8^3 cell order), eb_rel %g, %s predictor per %d-value block"
+                               % (n, args.eb, args.policy, 1 << args.block_log2),
+                   "particles": n, "fields": 6, "eb_rel": args.eb, "block": 1 << args.block_log2,
+                   "policy": args.policy},
+        "compress_GBps": round(4.0 * n_total / (c_ms * 1e-3) / 1e9, 2),
+        "decompress_GBps": round(4.0 * n_total / (d_ms * 1e-3) / 1e9, 2),
+        "ratio": round(ratio, 4),
+        "field_ratios": {k: round(4.0 * n / s, 3) for k, s in zip(names, sizes)},
+        "max_err_over_eb": round(worst, 6),
+        "roofline": roof,
+        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(kern.items())},
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(args.cpu_sample, n)
+        sample = [h[:m].copy() for h in host]
+        t1 = time.perf_counter()
+        streams = [oracle.compress(s, args.eb, mode) for s in sample]
+        t2 = time.perf_counter()
+        for s in streams:
+            oracle.decompress(s)
+        t3 = time.perf_counter()
+        # the same sample through the GPU path must give the same bytes
+        got = sznb.compress_batch([torch.from_numpy(s).to(dev) for s in sample], args.eb, mode)
+        exact = all(bytes(g.cpu().numpy()) == r for g, r in zip(got, streams))
+        out["cpu_baseline"] = {"value": round(4.0 * m * len(sample) / (t3 - t1) / 1e9, 5), "unit": "GB/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": "first %d values of each of the 6 fields, compress + decompress "
+                                         "(compress %.2fs, decompress %.2fs)" % (m, t2 - t1, t3 - t2),
+                               "gpu_bytes_identical_on_sample": exact}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

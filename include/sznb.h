@@ -1,0 +1,127 @@
+/*
+ * sznb -- error-bounded lossy compression of 1D float32 particle fields on
+ * AMD MI355X (gfx950).
+ *
+ * The method is the SZ-style pipeline the paper studies for N-body snapshots
+ * (Tao, Di, Chen, Cappello, "In-Depth Exploration of Single-Snapshot Lossy
+ * Compression Techniques for N-Body Simulations"):
+ *   - prediction of each value from preceding values: last value (Sec. 5.1,
+ *     the LV model), linear curve fit (Sec. 5.1, the LCF model) and its
+ *     quadratic extension, the best fit chosen per block;
+ *   - linear-scaling quantization of the prediction error into intervals of
+ *     width 2*eb, 65536 intervals (Sec. 5.1);
+ *   - Huffman coding of the quantization codes (Sec. 2; Sec. 5.2);
+ *   - decompression that restores every value within the bound (Problem
+ *     Statement: |x_i - x~_i| <= eb_abs, eb_rel = eb_abs / R).
+ *
+ * Every function is a plain C entry point over raw pointers.  "d_" pointers
+ * are device (HBM) pointers, "h_" pointers are host pointers.  The caller
+ * owns every buffer; the library never allocates device memory in these
+ * calls.  Work is enqueued on `stream` (0 = default stream) and the calls
+ * return without waiting for the GPU unless stated otherwise.
+ *
+ * Errors: argument errors found on the host are returned at once.  Errors
+ * that depend on the data (non-finite input, a bound below float32
+ * resolution, an output buffer that is too small, a corrupt stream) are found
+ * on the GPU: the call returns SZNB_OK, the field's output length is set to
+ * 0, and the per-field status is written into the workspace, where
+ * sznb_read_status() reads it back (it synchronises the stream).
+ */
+#ifndef SZNB_H
+#define SZNB_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SZNB_OK 0
+#define SZNB_EINVAL (-1)          /* bad argument (eb <= 0 or not finite, bad mode, n too large) */
+#define SZNB_ENONFINITE (-2)      /* the field holds NaN or Inf */
+#define SZNB_EEBTOOSMALL (-3)     /* bound below float32 resolution, or more than 2^27 lattice steps */
+#define SZNB_ENOSPC (-4)          /* output buffer or workspace too small */
+#define SZNB_ECORRUPT (-5)        /* stream fails validation */
+#define SZNB_EDEVICE (-6)         /* HIP runtime error */
+
+/* mode bits of sznb_compress */
+#define SZNB_PRED_LV 0u           /* last-value predictor on every block (the paper's SZ-LV) */
+#define SZNB_PRED_LCF 1u          /* linear curve fit on every block (original 1D SZ) */
+#define SZNB_PRED_BESTFIT 2u      /* LV / LCF / QCF chosen per block by exhaustive trial */
+#define SZNB_PRED_LEARNED 3u      /* per-block choice by the learned selector, trial as fallback */
+#define SZNB_EB_REL (1u << 4)     /* eb is relative to the field's value range R = max - min */
+#define SZNB_BLOCK_LOG2(b) ((uint32_t)(b) << 8) /* block size 2^b, b in 10..14; 0 = 4096 */
+
+#define SZNB_MAX_N ((uint64_t)1 << 31)   /* fields hold fewer than 2^31 values */
+#define SZNB_HEADER_BYTES 128u
+
+/* Worst-case stream size for a field of n values compressed with `mode`. */
+uint64_t sznb_compress_bound(uint64_t n, uint32_t mode);
+
+/* Smallest output capacity the device path accepts (header, block tables,
+ * codebooks).  Payload beyond out_cap is reported as SZNB_ENOSPC. */
+uint64_t sznb_compress_min_capacity(uint64_t n, uint32_t mode);
+
+/* Workspace bytes for compressing the nf fields of sizes n[] with modes
+ * mode[] in one call.  No initial contents are required: every call clears
+ * what it needs. */
+uint64_t sznb_compress_workspace_bytes(int nf, const uint64_t *h_n, const uint32_t *h_mode);
+
+/* Compress one field d_field[0..n) under the bound eb (absolute, or relative
+ * to the value range when mode has SZNB_EB_REL) into d_out[0..out_cap).
+ * The stream length is written to the device word *d_out_len (0 on error).
+ * Stream layout: 128-byte header, block tables, one canonical Huffman
+ * codebook per predictor in use, and the payload; see the design notes. */
+int sznb_compress(const float *d_field, uint64_t n, double eb, uint32_t mode,
+                  void *d_out, uint64_t out_cap, uint64_t *d_out_len,
+                  void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Compress nf fields in one batched launch sequence.  Arrays are host arrays
+ * of length nf holding device pointers (fields, outputs) and per-field
+ * parameters; d_lens is a device array of nf stream lengths.  All fields must
+ * use the same block size. */
+int sznb_compress_batch(int nf, const float *const *h_fields, const uint64_t *h_n,
+                        const double *h_eb, const uint32_t *h_mode,
+                        void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Parse a stream header held in host memory. */
+int sznb_stream_info(const void *h_hdr, uint64_t hdr_len, uint64_t *n, uint32_t *mode,
+                     double *eb_abs, uint64_t *total_bytes);
+
+/* Workspace bytes for decompressing nf streams whose fields hold n[] values. */
+uint64_t sznb_decompress_workspace_bytes(int nf, const uint64_t *h_n);
+
+/* Decompress the stream d_stream[0..stream_len) into d_out[0..n), where n is
+ * the field size stored in the stream (checked on the device). */
+int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n,
+                    void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Decompress nf streams in one batched launch sequence. */
+int sznb_decompress_batch(int nf, const void *const *h_streams, const uint64_t *h_lens,
+                          float *const *h_outs, const uint64_t *h_n,
+                          void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Per-field device status of the last call that used d_ws: waits for
+ * `stream`, copies nf status words to h_status.  Returns the first non-OK
+ * status, or SZNB_OK. */
+int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream);
+
+const char *sznb_strerror(int status);
+
+/* Measurement hooks.  sznb_profile(1) clears the record and brackets every
+ * later kernel launch with a pair of HIP events on the launch stream;
+ * sznb_profile(0) stops recording.  sznb_profile_summary() waits for the
+ * recorded events and writes, per kernel, its name (32-byte slots in
+ * `names`), the summed duration in milliseconds and the launch count; it
+ * returns the number of distinct kernels (entries beyond max_kernels are
+ * dropped). */
+int sznb_profile(int enable);
+int sznb_profile_summary(int max_kernels, char *names, double *total_ms, int *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SZNB_H */

@@ -1,0 +1,507 @@
+// Host side of the sznb C ABI: argument checks, workspace layout, launches.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sznb_internal.h"
+
+namespace sznb {
+
+// kernels (defined in sznb_compress.hip / sznb_decompress.hip)
+__global__ void k_init(const CField *, int, GCtl *, uint64_t *, uint64_t);
+__global__ void k_range(const CField *, int, const uint64_t *, uint64_t);
+__global__ void k_params(const CField *);
+template <int E> __global__ void k_quant(const CField *, int, const uint64_t *, uint64_t, const uint32_t *);
+__global__ void k_huff(const CField *, int, uint8_t *, uint64_t);
+__global__ void k_books(const CField *);
+template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, uint64_t, GCtl *);
+uint64_t hscratch_bytes_host();
+
+__global__ void d_prep(const DField *);
+__global__ void d_tables(const DField *);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *);
+__global__ void d_const(const DField *, int);
+__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t);
+
+constexpr uint64_t kStateStride = 256;
+
+// ------------------------------------------------------------ profiling
+// When enabled, every launch is bracketed by HIP events recorded on the
+// caller's stream; sznb_profile_summary() aggregates them per kernel.
+struct ProfRec {
+  const char *name;
+  hipEvent_t a, b;
+};
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_evpool;
+static size_t g_evnext = 0;
+static bool g_prof_on = false;
+
+static hipEvent_t prof_event() {
+  if (g_evnext == g_evpool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_evpool.push_back(e);
+  }
+  return g_evpool[g_evnext++];
+}
+struct ProfScope {
+  hipEvent_t b = nullptr;
+  const char *name;
+  hipStream_t s;
+  ProfScope(const char *n, hipStream_t st) : name(n), s(st) {
+    if (!g_prof_on) return;
+    hipEvent_t a = prof_event();
+    b = prof_event();
+    if (!a || !b) { b = nullptr; return; }
+    hipEventRecord(a, s);
+    g_prof.push_back({name, a, b});
+  }
+  ~ProfScope() {
+    if (b) hipEventRecord(b, s);
+  }
+};
+#define SZNB_LAUNCH(name, kernel, grid, block, lds, stream, ...)        \
+  do {                                                                  \
+    ProfScope _ps(name, stream);                                        \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__); \
+  } while (0)
+static_assert(sizeof(FState) <= kStateStride, "FState too large");
+static_assert(sizeof(DState) <= kStateStride, "DState too large");
+
+__device__ uint32_t g_logt[16385];
+
+struct DevInfo {
+  int ok = 0;
+  int cus = 0;
+  size_t lds_per_block = 0;
+};
+static DevInfo g_dev[64];
+static std::mutex g_mu;
+
+static int dev_init(DevInfo **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SZNB_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_mu);
+  DevInfo &d = g_dev[dev];
+  if (!d.ok) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return SZNB_EDEVICE;
+    d.cus = p.multiProcessorCount;
+    d.lds_per_block = p.sharedMemPerBlock;
+    // LOG[m] = round(2^16 log2 m): the fixed-point log of the block-cost estimate
+    std::vector<uint32_t> t(16385, 0u);
+    for (int m = 1; m <= 16384; m++) t[m] = (uint32_t)std::floor(65536.0 * std::log2((double)m) + 0.5);
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_logt), t.data(), t.size() * sizeof(uint32_t)) != hipSuccess) return SZNB_EDEVICE;
+    if (hipDeviceSynchronize() != hipSuccess) return SZNB_EDEVICE;
+    d.ok = 1;
+  }
+  *out = &d;
+  return SZNB_OK;
+}
+
+static inline uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+static int block_log2_of(uint32_t mode) {
+  uint32_t b = (mode >> 8) & 15u;
+  return b == 0 ? 12 : (int)b;
+}
+static bool mode_ok(uint32_t mode) {
+  if (mode & ~(uint32_t)(3u | 16u | (15u << 8))) return false;
+  int bl = block_log2_of(mode);
+  return bl >= 10 && bl <= 14;
+}
+
+// ----------------------------------------------------------- compress plan
+
+struct CLayout {
+  uint64_t gctl, states, fields, fb0, blkstat, lbflag, perfield_base, hscratch, total;
+  std::vector<uint64_t> hist, enc, book, nblocks, gblock0, nhist;
+  uint64_t total_blocks;
+  int nslots;
+};
+
+static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) {
+  CLayout L;
+  uint64_t o = 0;
+  L.gctl = o; o = al256(o + sizeof(GCtl));
+  L.states = o; o = al256(o + kStateStride * nf);
+  L.fields = o; o = al256(o + sizeof(CField) * nf);
+  L.fb0 = o; o = al256(o + 8ull * (nf + 1));
+  L.total_blocks = 0;
+  L.nblocks.resize(nf); L.gblock0.resize(nf); L.nhist.resize(nf);
+  int npairs = 0;
+  for (int f = 0; f < nf; f++) {
+    const uint64_t S = 1ull << block_log2_of(mode[f]);
+    L.nblocks[f] = (n[f] + S - 1) / S;
+    L.gblock0[f] = L.total_blocks;
+    L.total_blocks += L.nblocks[f];
+    L.nhist[f] = (mode[f] & 3u) >= 2 ? 3 : 1;
+    npairs += (int)L.nhist[f];
+  }
+  L.blkstat = o; o = al256(o + 12ull * L.total_blocks);
+  L.lbflag = o; o = al256(o + 8ull * L.total_blocks);
+  L.hist.resize(nf); L.enc.resize(nf); L.book.resize(nf);
+  for (int f = 0; f < nf; f++) {
+    L.hist[f] = o; o = al256(o + 4ull * kNSyms * L.nhist[f]);
+    L.enc[f] = o; o = al256(o + 4ull * kNSyms * L.nhist[f]);
+    L.book[f] = o; o = al256(o + 4ull * kBookWords * L.nhist[f]);
+  }
+  L.nslots = npairs < 64 ? (npairs > 0 ? npairs : 1) : 64;
+  L.hscratch = o; o = al256(o + hscratch_bytes_host() * (uint64_t)L.nslots);
+  L.total = o;
+  return L;
+}
+
+static uint64_t compress_bound_impl(uint64_t n, uint32_t mode) {
+  const uint64_t S = 1ull << block_log2_of(mode);
+  const uint64_t nb = (n + S - 1) / S;
+  Sections s = sections_of(nb, (int)(mode & 3u));
+  const uint64_t books = 3 * align8(4ull * kLMax + 2ull * kNSyms);
+  const uint64_t cwmax = S * kLMax / 32;
+  return s.books + books + 4ull * nb * (cwmax + S);
+}
+
+static uint64_t compress_min_cap_impl(uint64_t n, uint32_t mode) {
+  const uint64_t S = 1ull << block_log2_of(mode);
+  const uint64_t nb = (n + S - 1) / S;
+  Sections s = sections_of(nb, (int)(mode & 3u));
+  return s.books + 3 * align8(4ull * kLMax + 2ull * kNSyms);
+}
+
+struct Launch {
+  int E;
+  uint64_t total_blocks;
+  int nf;
+  int nslots;
+  uint8_t *ws;
+  CLayout L;
+};
+
+template <int E>
+static void launch_quant_pack(bool quant, const Launch &P, hipStream_t s, int grid) {
+  const CField *F = reinterpret_cast<const CField *>(P.ws + P.L.fields);
+  const uint64_t *fb0 = reinterpret_cast<const uint64_t *>(P.ws + P.L.fb0);
+  if (quant) {
+    uint32_t *logt = nullptr;
+    (void)hipGetSymbolAddress(reinterpret_cast<void **>(&logt), HIP_SYMBOL(g_logt));
+    SZNB_LAUNCH("k_quant", k_quant<E>, dim3(grid), dim3(kThreads), 0, s, F, P.nf, fb0, P.total_blocks, logt);
+  } else {
+    SZNB_LAUNCH("k_pack", k_pack<E>, dim3(grid), dim3(kThreads), 0, s, F, P.nf, fb0, P.total_blocks,
+                reinterpret_cast<GCtl *>(P.ws + P.L.gctl));
+  }
+}
+
+static void launch_E(bool quant, const Launch &P, hipStream_t s, int grid) {
+  switch (P.E) {
+    case 4: launch_quant_pack<4>(quant, P, s, grid); break;
+    case 8: launch_quant_pack<8>(quant, P, s, grid); break;
+    case 16: launch_quant_pack<16>(quant, P, s, grid); break;
+    case 32: launch_quant_pack<32>(quant, P, s, grid); break;
+    default: launch_quant_pack<64>(quant, P, s, grid); break;
+  }
+}
+
+// waves per CU used for the persistent per-block kernels (tunable)
+static int g_wg_per_cu = 8;
+
+static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv) {
+  const CField *F = reinterpret_cast<const CField *>(P.ws + P.L.fields);
+  const uint64_t *fb0 = reinterpret_cast<const uint64_t *>(P.ws + P.L.fb0);
+  GCtl *gc = reinterpret_cast<GCtl *>(P.ws + P.L.gctl);
+  uint64_t *lb = reinterpret_cast<uint64_t *>(P.ws + P.L.lbflag);
+  const uint64_t tb = P.total_blocks;
+  const int ginit = 1024;
+  SZNB_LAUNCH("k_init", k_init, dim3(ginit), dim3(kThreads), 0, s, F, P.nf, gc, lb, tb);
+  int gper = (int)std::min<uint64_t>((uint64_t)dv->cus * g_wg_per_cu, std::max<uint64_t>(tb, 1));
+  if (gper > 8) gper &= ~7;  // multiple of the XCD count keeps a block on one XCD across passes
+  if (tb) SZNB_LAUNCH("k_range", k_range, dim3(gper), dim3(kThreads), 0, s, F, P.nf, fb0, tb);
+  SZNB_LAUNCH("k_params", k_params, dim3(P.nf), dim3(kThreads), 0, s, F);
+  if (tb) launch_E(true, P, s, gper);
+  SZNB_LAUNCH("k_huff", k_huff, dim3(P.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host());
+  SZNB_LAUNCH("k_books", k_books, dim3(P.nf), dim3(kThreads), 0, s, F);
+  if (tb) launch_E(false, P, s, gper);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+static int compress_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
+                         const uint32_t *mode, void *const *outs, const uint64_t *caps, uint64_t *d_lens,
+                         bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (nf <= 0 || !d_ws) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  uint32_t s0 = 0;
+  for (int f = 0; f < nf; f++) {
+    if (!mode_ok(mode[f]) || !(eb[f] > 0.0) || !std::isfinite(eb[f]) || n[f] >= SZNB_MAX_N) return SZNB_EINVAL;
+    if (n[f] && (!fields[f] || (reinterpret_cast<uintptr_t>(fields[f]) & 15u))) return SZNB_EINVAL;
+    if (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 7u)) return SZNB_EINVAL;
+    if (caps[f] < compress_min_cap_impl(n[f], mode[f])) return SZNB_ENOSPC;
+    const uint32_t bl = (uint32_t)block_log2_of(mode[f]);
+    if (f == 0) s0 = bl; else if (bl != s0) return SZNB_EINVAL;
+  }
+  CLayout L = compress_layout(nf, n, mode);
+  if (ws_bytes < L.total) return SZNB_ENOSPC;
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  std::vector<CField> hf(nf);
+  std::vector<uint64_t> fb0(nf + 1);
+  for (int f = 0; f < nf; f++) {
+    CField &c = hf[f];
+    std::memset(&c, 0, sizeof c);
+    const int bl = block_log2_of(mode[f]);
+    c.x = fields[f];
+    c.n = n[f];
+    c.eb = eb[f];
+    c.out = static_cast<uint8_t *>(outs[f]);
+    c.out_cap = caps[f];
+    c.out_len = d_lens ? (lens_is_array ? d_lens + f : d_lens) : nullptr;
+    c.policy = mode[f] & 3u;
+    c.eb_rel = (mode[f] >> 4) & 1u;
+    c.S = 1u << bl;
+    c.log2S = (uint32_t)bl;
+    c.nblocks = (uint32_t)L.nblocks[f];
+    c.nhist = (uint32_t)L.nhist[f];
+    c.gblock0 = L.gblock0[f];
+    c.sec = sections_of(L.nblocks[f], (int)c.policy);
+    c.st = reinterpret_cast<FState *>(ws + L.states + kStateStride * f);
+    c.blkstat = reinterpret_cast<uint32_t *>(ws + L.blkstat) + 3 * L.gblock0[f];
+    c.hist = reinterpret_cast<uint32_t *>(ws + L.hist[f]);
+    c.enc = reinterpret_cast<uint32_t *>(ws + L.enc[f]);
+    c.book = reinterpret_cast<uint32_t *>(ws + L.book[f]);
+    c.lbflag = reinterpret_cast<uint64_t *>(ws + L.lbflag) + L.gblock0[f];
+    fb0[f] = L.gblock0[f];
+  }
+  fb0[nf] = L.total_blocks;
+  if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(CField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return SZNB_EDEVICE;
+  if (hipMemcpyAsync(ws + L.fb0, fb0.data(), 8ull * (nf + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return SZNB_EDEVICE;
+  // pageable source buffers must stay valid until the copies are consumed
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  Launch P;
+  P.E = (int)((1u << s0) / kThreads);
+  P.total_blocks = L.total_blocks;
+  P.nf = nf;
+  P.nslots = L.nslots;
+  P.ws = ws;
+  P.L = L;
+  return compress_run(P, stream, dv);
+}
+
+// ---------------------------------------------------------- decompress
+
+struct DLayout {
+  uint64_t gctl, states, fields, tbase, total;
+  std::vector<uint64_t> boff, order, lut, slow, syms, nbmax;
+};
+
+static DLayout decompress_layout(int nf, const uint64_t *n) {
+  DLayout L;
+  uint64_t o = 0;
+  L.gctl = o; o = al256(o + sizeof(GCtl));
+  L.states = o; o = al256(o + kStateStride * nf);
+  L.fields = o; o = al256(o + sizeof(DField) * nf);
+  L.tbase = o; o = al256(o + 4ull * (3 * nf + 1));
+  L.boff.resize(nf); L.order.resize(nf); L.lut.resize(nf); L.slow.resize(nf); L.syms.resize(nf); L.nbmax.resize(nf);
+  for (int f = 0; f < nf; f++) {
+    L.nbmax[f] = (n[f] + 1023) / 1024;
+    L.boff[f] = o; o = al256(o + 4ull * L.nbmax[f]);
+    L.order[f] = o; o = al256(o + 4ull * L.nbmax[f]);
+    L.lut[f] = o; o = al256(o + 4ull * 3 * (1u << kLutBits));
+    L.slow[f] = o; o = al256(o + 4ull * 3 * kSlowWords);
+    L.syms[f] = o; o = al256(o + 2ull * 3 * kNSyms);
+  }
+  L.total = o;
+  return L;
+}
+
+static int decompress_impl(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
+                           const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (nf <= 0 || !d_ws) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  DLayout L = decompress_layout(nf, n);
+  if (ws_bytes < L.total) return SZNB_ENOSPC;
+  // block sizes from the headers (host copy of 128 bytes per stream)
+  std::vector<uint8_t> hdr(128ull * nf);
+  for (int f = 0; f < nf; f++) {
+    if (!streams[f] || lens[f] < kHdr || (reinterpret_cast<uintptr_t>(streams[f]) & 7u)) return SZNB_EINVAL;
+    if (n[f] && (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 15u))) return SZNB_EINVAL;
+    if (n[f] >= SZNB_MAX_N) return SZNB_EINVAL;
+    if (hipMemcpyAsync(hdr.data() + 128ull * f, streams[f], 128, hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return SZNB_EDEVICE;
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  uint32_t smax = 1024;
+  for (int f = 0; f < nf; f++) {
+    uint32_t S;
+    std::memcpy(&S, hdr.data() + 128ull * f + H_S, 4);
+    if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
+  }
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  std::vector<DField> hf(nf);
+  for (int f = 0; f < nf; f++) {
+    DField &d = hf[f];
+    std::memset(&d, 0, sizeof d);
+    d.in = static_cast<const uint8_t *>(streams[f]);
+    d.in_len = lens[f];
+    d.out = outs[f];
+    d.n = n[f];
+    d.nblocks_max = (uint32_t)L.nbmax[f];
+    d.st = reinterpret_cast<DState *>(ws + L.states + kStateStride * f);
+    d.boff = reinterpret_cast<uint32_t *>(ws + L.boff[f]);
+    d.order = reinterpret_cast<uint32_t *>(ws + L.order[f]);
+    d.lut = reinterpret_cast<uint32_t *>(ws + L.lut[f]);
+    d.slow = reinterpret_cast<uint32_t *>(ws + L.slow[f]);
+    d.syms = reinterpret_cast<uint16_t *>(ws + L.syms[f]);
+  }
+  if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(DField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return SZNB_EDEVICE;
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  const DField *D = reinterpret_cast<const DField *>(ws + L.fields);
+  uint32_t *tbase = reinterpret_cast<uint32_t *>(ws + L.tbase);
+  SZNB_LAUNCH("d_prep", d_prep, dim3(nf), dim3(kThreads), 0, stream, D);
+  SZNB_LAUNCH("d_tables", d_tables, dim3(3 * nf), dim3(kThreads), 0, stream, D);
+  // waves per workgroup: regions of 4*smax bytes next to the tables
+  uint32_t dw = 8192u / smax;
+  if (dw < 1) dw = 1;
+  if (dw > 4) dw = 4;
+  const size_t lds = 4ull * (1u << kLutBits) + 4ull * kSlowWords + 4ull * smax * dw;
+  if (lds > 65536) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(d_decode), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+      return SZNB_EDEVICE;
+  }
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, nf, dw, tbase);
+  SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, nf);
+  const int grid = dv->cus * 4;
+  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+}  // namespace sznb
+
+using namespace sznb;
+
+extern "C" {
+
+uint64_t sznb_compress_bound(uint64_t n, uint32_t mode) { return compress_bound_impl(n, mode); }
+
+uint64_t sznb_compress_min_capacity(uint64_t n, uint32_t mode) { return compress_min_cap_impl(n, mode); }
+
+uint64_t sznb_compress_workspace_bytes(int nf, const uint64_t *h_n, const uint32_t *h_mode) {
+  if (nf <= 0) return 0;
+  return compress_layout(nf, h_n, h_mode).total;
+}
+
+int sznb_compress(const float *d_field, uint64_t n, double eb, uint32_t mode, void *d_out, uint64_t out_cap,
+                  uint64_t *d_out_len, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  void *outs[1] = {d_out};
+  return compress_impl(1, &d_field, &n, &eb, &mode, outs, &out_cap, d_out_len, false, d_ws, ws_bytes, stream);
+}
+
+int sznb_compress_batch(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                        const uint32_t *h_mode, void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  return compress_impl(nf, h_fields, h_n, h_eb, h_mode, h_outs, h_caps, d_lens, true, d_ws, ws_bytes, stream);
+}
+
+int sznb_stream_info(const void *h_hdr, uint64_t hdr_len, uint64_t *n, uint32_t *mode, double *eb_abs,
+                     uint64_t *total_bytes) {
+  if (!h_hdr || hdr_len < kHdr) return SZNB_EINVAL;
+  const uint8_t *h = static_cast<const uint8_t *>(h_hdr);
+  uint32_t magic;
+  uint16_t ver;
+  std::memcpy(&magic, h, 4);
+  std::memcpy(&ver, h + 4, 2);
+  if (magic != kMagic || ver != 1) return SZNB_ECORRUPT;
+  uint32_t S;
+  std::memcpy(&S, h + H_S, 4);
+  int bl = 0;
+  while ((1u << bl) < S && bl < 31) bl++;
+  if (n) std::memcpy(n, h + H_N, 8);
+  if (mode) *mode = (uint32_t)h[H_POLICY] | ((h[H_FLAGS] & 2u) ? SZNB_EB_REL : 0u) | SZNB_BLOCK_LOG2(bl);
+  if (eb_abs) std::memcpy(eb_abs, h + H_EBABS, 8);
+  if (total_bytes) std::memcpy(total_bytes, h + H_TOTAL, 8);
+  return SZNB_OK;
+}
+
+uint64_t sznb_decompress_workspace_bytes(int nf, const uint64_t *h_n) {
+  if (nf <= 0) return 0;
+  return decompress_layout(nf, h_n).total;
+}
+
+int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n, void *d_ws,
+                    uint64_t ws_bytes, hipStream_t stream) {
+  float *outs[1] = {d_out};
+  return decompress_impl(1, &d_stream, &stream_len, outs, &n, d_ws, ws_bytes, stream);
+}
+
+int sznb_decompress_batch(int nf, const void *const *h_streams, const uint64_t *h_lens, float *const *h_outs,
+                          const uint64_t *h_n, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  return decompress_impl(nf, h_streams, h_lens, h_outs, h_n, d_ws, ws_bytes, stream);
+}
+
+int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream) {
+  if (!d_ws || nf <= 0 || !h_status) return SZNB_EINVAL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  const uint8_t *base = static_cast<const uint8_t *>(d_ws) + al256(sizeof(GCtl));
+  int first = SZNB_OK;
+  for (int f = 0; f < nf; f++) {
+    int32_t v = 0;
+    if (hipMemcpy(&v, base + kStateStride * f, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
+    h_status[f] = v;
+    if (v != SZNB_OK && first == SZNB_OK) first = v;
+  }
+  return first;
+}
+
+int sznb_profile(int enable) {
+  if (enable) {
+    g_prof.clear();
+    g_evnext = 0;
+  }
+  g_prof_on = enable != 0;
+  return SZNB_OK;
+}
+
+int sznb_profile_summary(int max_kernels, char *names, double *total_ms, int *count) {
+  std::vector<const char *> keys;
+  std::vector<double> tot;
+  std::vector<int> cnt;
+  for (const ProfRec &r : g_prof) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return SZNB_EDEVICE;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return SZNB_EDEVICE;
+    size_t i = 0;
+    while (i < keys.size() && std::strcmp(keys[i], r.name) != 0) i++;
+    if (i == keys.size()) { keys.push_back(r.name); tot.push_back(0.0); cnt.push_back(0); }
+    tot[i] += ms;
+    cnt[i] += 1;
+  }
+  const int nk = (int)keys.size();
+  for (int i = 0; i < nk && i < max_kernels; i++) {
+    std::strncpy(names + 32 * i, keys[i], 31);
+    names[32 * i + 31] = 0;
+    total_ms[i] = tot[i];
+    count[i] = cnt[i];
+  }
+  return nk;
+}
+
+const char *sznb_strerror(int status) {
+  switch (status) {
+    case SZNB_OK: return "ok";
+    case SZNB_EINVAL: return "invalid argument";
+    case SZNB_ENONFINITE: return "field holds NaN or Inf";
+    case SZNB_EEBTOOSMALL: return "error bound below float32 resolution or lattice too large";
+    case SZNB_ENOSPC: return "output buffer or workspace too small";
+    case SZNB_ECORRUPT: return "corrupt stream";
+    case SZNB_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,925 @@
+// Compression kernels of the sznb library (gfx950, wave64).
+//
+// Pipeline over a table of fields (one field or a batch share the code):
+//   k_init    clear per-call state (look-back words, tickets, counters)
+//   k_range   per-block exact min / max / non-finite flag      (reads 4 B/value)
+//   k_params  per-field range R, bound, lattice step, header    (Problem Statement)
+//   k_quant   lattice quantization, LV/LCF/QCF residuals, per-block best-fit
+//             trial, one code histogram per predictor          (reads 4 B/value)
+//   k_huff    canonical Huffman code per (field, predictor)     (Sec. 2 / 5.2)
+//   k_books   codebook sections and payload offset of each stream
+//   k_pack    codewords, block bit counts, decoupled look-back scan of block
+//             sizes, MSB-first bit packing, escapes             (reads 4 B/value,
+//             writes the payload)
+#include "sznb_internal.h"
+
+namespace sznb {
+
+constexpr int kWin = 2048;  // LDS window of the code histogram around code 32768
+
+// ------------------------------------------------------------------ init
+
+__global__ void k_init(const CField *__restrict__ F, int nf, GCtl *gc, uint64_t *lbflag_all,
+                       uint64_t total_blocks) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (tid == 0) gc->ticket = 0;
+  for (uint64_t i = tid; i < (uint64_t)nf; i += stride) {
+    FState *s = F[i].st;
+    s->status = 0;
+    s->is_const = 0;
+    s->blocks_done = 0;
+    s->payload_words = 0;
+    s->off_payload = 0;
+    for (int k = 0; k < 3; k++) { s->nsym[k] = 0; s->maxlen[k] = 0; }
+  }
+  for (uint64_t g = tid; g < total_blocks; g += stride) lbflag_all[g] = 0;
+  // code histograms start from zero on every call
+  for (int f = 0; f < nf; f++) {
+    uint4 *h = reinterpret_cast<uint4 *>(F[f].hist);
+    const uint64_t n4 = (uint64_t)F[f].nhist * kNSyms / 4;
+    for (uint64_t i = tid; i < n4; i += stride) h[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+// ----------------------------------------------------------------- range
+
+__global__ __launch_bounds__(kThreads) void k_range(const CField *__restrict__ F, int nf,
+                                                    const uint64_t *__restrict__ fb0, uint64_t total) {
+  __shared__ uint32_t s_mn[kThreads / kWave], s_mx[kThreads / kWave], s_bad[kThreads / kWave];
+  const int t = threadIdx.x, w = t / kWave;
+  for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int f = find_field(fb0, nf, g);
+    const CField &c = F[f];
+    const uint64_t b = g - c.gblock0;
+    const uint64_t i0 = b << c.log2S;
+    const uint32_t len = (uint32_t)min((uint64_t)c.S, c.n - i0);
+    const float *x = c.x + i0;
+    uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
+    for (uint32_t j = 4u * t; j < len; j += 4u * kThreads) {
+      float v[4];
+      if (j + 4 <= len) {
+        float4 q = *reinterpret_cast<const float4 *>(x + j);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+      } else {
+        for (int e = 0; e < 4; e++) v[e] = j + e < len ? x[j + e] : x[j];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        if (!isfinite(v[e])) { bad = 1u; continue; }
+        uint32_t k = float_key(v[e]);
+        mn = min(mn, k);
+        mx = max(mx, k);
+      }
+    }
+    mn = wave_min_u32(mn);
+    mx = wave_max_u32(mx);
+    bad = wave_max_u32(bad);
+    if ((t & (kWave - 1)) == 0) { s_mn[w] = mn; s_mx[w] = mx; s_bad[w] = bad; }
+    __syncthreads();
+    if (t == 0) {
+      for (int i = 1; i < kThreads / kWave; i++) {
+        mn = min(mn, s_mn[i]);
+        mx = max(mx, s_mx[i]);
+        bad |= s_bad[i];
+      }
+      c.blkstat[3 * b + 0] = mn;
+      c.blkstat[3 * b + 1] = mx;
+      c.blkstat[3 * b + 2] = bad;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- params
+
+__device__ inline void put32(uint8_t *o, uint64_t off, uint32_t v) { *reinterpret_cast<uint32_t *>(o + off) = v; }
+__device__ inline void put64(uint8_t *o, uint64_t off, uint64_t v) {
+  put32(o, off, (uint32_t)v);
+  put32(o, off + 4, (uint32_t)(v >> 32));
+}
+__device__ inline void putf64(uint8_t *o, uint64_t off, double v) { put64(o, off, (uint64_t)__double_as_longlong(v)); }
+
+// One workgroup per field: reduce the block extrema, derive the bound and the
+// lattice step, write the fixed part of the header.
+//   R = max - min; eb_abs = eb_rel * R when relative (Problem Statement).
+//   step = 2 (eb_abs - g), g = 2 ulp_f32(max |x|): the float32 rounding of the
+//   reconstructed value then never carries the error past eb_abs.
+__global__ __launch_bounds__(kThreads) void k_params(const CField *__restrict__ F) {
+  __shared__ uint32_t s_mn[kThreads], s_mx[kThreads], s_bad[kThreads];
+  const CField &c = F[blockIdx.x];
+  FState *st = c.st;
+  const int t = threadIdx.x;
+  uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
+  for (uint32_t b = t; b < c.nblocks; b += kThreads) {
+    mn = min(mn, c.blkstat[3 * b]);
+    mx = max(mx, c.blkstat[3 * b + 1]);
+    bad |= c.blkstat[3 * b + 2];
+  }
+  s_mn[t] = mn; s_mx[t] = mx; s_bad[t] = bad;
+  __syncthreads();
+  for (int h = kThreads / 2; h > 0; h >>= 1) {
+    if (t < h) {
+      s_mn[t] = min(s_mn[t], s_mn[t + h]);
+      s_mx[t] = max(s_mx[t], s_mx[t + h]);
+      s_bad[t] |= s_bad[t + h];
+    }
+    __syncthreads();
+  }
+  __shared__ int s_ok;
+  uint8_t *o = c.out;
+  if (t == 0) {
+    int status = 0;
+    uint32_t is_const = 0;
+    float fmn = 0.0f, fmx = 0.0f;
+    double R = 0.0, eb_abs = 0.0, step = 0.0, inv = 0.0;
+    int64_t P = 0;
+    if (c.n == 0) {
+      is_const = 1;
+    } else if (s_bad[0]) {
+      status = SZNB_ENONFINITE;
+    } else {
+      fmn = key_float(s_mn[0]);
+      fmx = key_float(s_mx[0]);
+      if (fmn == 0.0f) fmn = 0.0f;
+      if (fmx == 0.0f) fmx = 0.0f;
+      R = __dsub_rn((double)fmx, (double)fmn);
+      eb_abs = c.eb_rel ? __dmul_rn(c.eb, R) : c.eb;
+      if (R == 0.0) {
+        is_const = 1;
+      } else {
+        float am = fabsf(fmn) > fabsf(fmx) ? fabsf(fmn) : fabsf(fmx);
+        double ebp = __dsub_rn(eb_abs, guard_of(am));
+        if (!(ebp > 0.0)) {
+          status = SZNB_EEBTOOSMALL;
+        } else {
+          step = __dmul_rn(2.0, ebp);
+          inv = __ddiv_rn(1.0, step);
+          double tt = __dmul_rn(__dsub_rn((double)fmx, (double)fmn), inv);
+          double Pd = floor(__dadd_rn(tt, 0.5));
+          if (Pd > (double)kPMax) status = SZNB_EEBTOOSMALL;
+          else P = (int64_t)Pd;
+        }
+      }
+    }
+    st->status = status;
+    st->is_const = is_const;
+    st->mn = fmn; st->mx = fmx; st->R = R; st->eb_abs = eb_abs; st->step = step; st->inv = inv; st->P = P;
+    s_ok = status == 0 && !is_const;
+    if (status != 0) {
+      if (c.out_len) *c.out_len = 0;
+    } else {
+      // header words 0..127
+      for (int i = 0; i < kHdr; i += 4) put32(o, i, 0u);
+      put32(o, H_MAGIC, kMagic);
+      put32(o, H_VERSION, (uint32_t)1 | ((uint32_t)c.policy << 16) |
+                              ((uint32_t)((is_const ? 1u : 0u) | (c.eb_rel << 1)) << 24));
+      put64(o, H_N, c.n);
+      put32(o, H_S, c.S);
+      put32(o, H_MN, __float_as_uint(fmn));
+      put32(o, H_MX, __float_as_uint(fmx));
+      putf64(o, H_EBABS, eb_abs);
+      if (is_const) {
+        put64(o, H_TOTAL, kHdr);
+        if (c.out_len) *c.out_len = kHdr;
+      } else {
+        put32(o, H_NB, c.nblocks);
+        putf64(o, H_STEP, step);
+        put64(o, H_OFF_PRED, c.sec.pred);
+        put64(o, H_OFF_PFIRST, c.sec.pfirst);
+        put64(o, H_OFF_CWORDS, c.sec.cwords);
+        put64(o, H_OFF_NESC, c.sec.nesc);
+        put64(o, H_OFF_BOOKS, c.sec.books);
+      }
+    }
+  }
+  __syncthreads();
+  if (s_ok) {
+    // zero the alignment padding after each fixed-size table
+    const uint64_t nb = c.nblocks;
+    if (t < 8) {
+      if (c.policy >= 2 && c.sec.pred + nb + t < c.sec.pfirst) o[c.sec.pred + nb + t] = 0;
+      if (c.sec.pfirst + 4 * nb + t < c.sec.cwords) o[c.sec.pfirst + 4 * nb + t] = 0;
+      if (c.sec.cwords + 2 * nb + t < c.sec.nesc) o[c.sec.cwords + 2 * nb + t] = 0;
+      if (c.sec.nesc + 2 * nb + t < c.sec.books) o[c.sec.nesc + 2 * nb + t] = 0;
+    }
+  }
+}
+
+// --------------------------------------------------- quantize and select
+
+// residual class of the best-fit estimate: zigzag z < 4 is its own class; a
+// larger z of bit length b is class 4 + 2(b-3) + (bit b-2 of z) with b-2
+// extra bits; an escape (|r| >= 32768) is class 32 with 32 extra bits.
+__device__ inline uint32_t res_class(int32_t r, uint32_t &extra) {
+  if (r >= kRadius || r <= -kRadius) { extra = 32u; return 32u; }
+  uint32_t z = ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+  if (z < 4u) { extra = 0u; return z; }
+  uint32_t b = 32u - __clz(z);
+  extra = b - 2u;
+  return 4u + 2u * (b - 3u) + ((z >> (b - 2u)) & 1u);
+}
+
+__device__ inline int32_t lattice_of(float x, float mn, double inv) {
+  double t = __dmul_rn(__dsub_rn((double)x, (double)mn), inv);
+  return (int32_t)floor(__dadd_rn(t, 0.5));
+}
+
+// Loads this thread's E contiguous values of the block, computes the lattice
+// index relative to the block anchor (d_j = p_j - p_0), and fetches the three
+// values that precede the thread's run (zero before the block start).
+template <int E>
+__device__ inline void load_block_d(const CField &c, const FState *st, uint64_t i0, uint32_t len,
+                                    int32_t (&d)[E], int32_t (&pv)[3], int32_t *s_tail, int32_t &p0_out,
+                                    int32_t *s_p0) {
+  const int t = threadIdx.x;
+  const float mn = st->mn;
+  const double inv = st->inv;
+  const float *x = c.x + i0 + (uint64_t)t * E;
+  float v[E];
+  if ((uint32_t)(t + 1) * E <= len) {
+#pragma unroll
+    for (int e = 0; e < E; e += 4) {
+      float4 q = *reinterpret_cast<const float4 *>(x + e);
+      v[e] = q.x; v[e + 1] = q.y; v[e + 2] = q.z; v[e + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; e++) v[e] = ((uint32_t)t * E + e < len) ? x[e] : mn;
+  }
+  int32_t p[E];
+#pragma unroll
+  for (int e = 0; e < E; e++) p[e] = lattice_of(v[e], mn, inv);
+  if (t == 0) *s_p0 = p[0];
+  __syncthreads();
+  const int32_t p0 = *s_p0;
+#pragma unroll
+  for (int e = 0; e < E; e++) d[e] = (int32_t)((uint32_t)p[e] - (uint32_t)p0);
+  s_tail[3 * t + 0] = d[E - 1];
+  s_tail[3 * t + 1] = d[E - 2];
+  s_tail[3 * t + 2] = d[E - 3];
+  __syncthreads();
+  if (t == 0) { pv[0] = pv[1] = pv[2] = 0; }
+  else { pv[0] = s_tail[3 * (t - 1)]; pv[1] = s_tail[3 * (t - 1) + 1]; pv[2] = s_tail[3 * (t - 1) + 2]; }
+  p0_out = p0;
+}
+
+// residual of predictor k at element e given the run d[] and its three
+// predecessors pv = (d_{-1}, d_{-2}, d_{-3})
+template <int E>
+__device__ inline int32_t residual_at(const int32_t (&d)[E], const int32_t (&pv)[3], int e, int k) {
+  auto D = [&](int i) -> uint32_t { return (uint32_t)(i >= 0 ? d[i] : pv[-i - 1]); };
+  uint32_t a0 = D(e) - D(e - 1);
+  if (k == 0) return (int32_t)a0;
+  uint32_t a1 = D(e - 1) - D(e - 2);
+  uint32_t b0 = a0 - a1;
+  if (k == 1) return (int32_t)b0;
+  uint32_t a2 = D(e - 2) - D(e - 3);
+  return (int32_t)(b0 - (a1 - a2));
+}
+
+template <int E>
+__global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F, int nf,
+                                                    const uint64_t *__restrict__ fb0, uint64_t total,
+                                                    const uint32_t *__restrict__ logt) {
+  constexpr int S = E * kThreads;
+  __shared__ int32_t s_tail[3 * kThreads];
+  __shared__ uint32_t s_cls[3 * kNClass];
+  __shared__ uint32_t s_extra[3];
+  __shared__ unsigned long long s_cost[3];
+  __shared__ int32_t s_p0;
+  __shared__ int s_pred;
+  __shared__ uint32_t s_win[3 * kWin];
+  const int t = threadIdx.x;
+  const uint32_t wbase = kRadius - kWin / 2;
+  int cur = -1;
+
+  auto flush = [&](int f) {
+    __syncthreads();
+    if (f >= 0) {
+      const CField &c = F[f];
+      for (uint32_t i = t; i < c.nhist * kWin; i += kThreads) {
+        uint32_t v = s_win[i];
+        if (v) atomicAdd(&c.hist[(i / kWin) * kNSyms + wbase + (i % kWin)], v);
+      }
+    }
+    for (uint32_t i = t; i < 3 * kWin; i += kThreads) s_win[i] = 0;
+    __syncthreads();
+  };
+
+  for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int f = find_field(fb0, nf, g);
+    const CField &c = F[f];
+    const FState *st = c.st;
+    if (st->status != 0 || st->is_const) continue;
+    if (f != cur) { flush(cur); cur = f; }
+    const uint64_t b = g - c.gblock0;
+    const uint64_t i0 = b * S;
+    const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
+    int32_t d[E], pv[3], p0;
+    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
+
+    int pred = (int)c.policy;
+    if (c.policy >= 2) {
+      if (t < 3 * kNClass) s_cls[t] = 0;
+      if (t < 3) { s_extra[t] = 0; s_cost[t] = 0; }
+      __syncthreads();
+      uint32_t ex[3] = {0u, 0u, 0u};
+#pragma unroll
+      for (int e = 0; e < E; e++) {
+        if ((uint32_t)t * E + e < len) {
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            uint32_t xb;
+            uint32_t cl = res_class(residual_at<E>(d, pv, e, k), xb);
+            atomicAdd(&s_cls[k * kNClass + cl], 1u);
+            ex[k] += xb;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        uint32_t v = wave_sum(ex[k]);
+        if ((t & (kWave - 1)) == 0) atomicAdd(&s_extra[k], v);
+      }
+      __syncthreads();
+      if (t < 3 * kNClass) {
+        uint32_t n_c = s_cls[t];
+        if (n_c) atomicAdd(&s_cost[t / kNClass], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]));
+      }
+      __syncthreads();
+      if (t == 0) {
+        int best = 0;
+        unsigned long long bc = 0;
+        for (int k = 0; k < 3; k++) {
+          unsigned long long ck = s_cost[k] + 65536ull * s_extra[k];
+          if (k == 0 || ck < bc) { bc = ck; best = k; }
+        }
+        s_pred = best;
+        c.out[c.sec.pred + b] = (uint8_t)best;
+      }
+      __syncthreads();
+      pred = s_pred;
+    }
+    if (t == 0) reinterpret_cast<int32_t *>(c.out + c.sec.pfirst)[b] = p0;
+
+    // code histogram of the chosen predictor
+    const int slot = c.policy >= 2 ? pred : 0;
+    uint32_t *win = s_win + slot * kWin;
+    uint32_t *gh = c.hist + (uint64_t)slot * kNSyms;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const bool valid = (uint32_t)t * E + e < len;
+      int32_t r = residual_at<E>(d, pv, e, pred);
+      uint32_t q = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
+      // the zero residual is aggregated per wave (it dominates smooth fields)
+      const uint64_t zmask = __ballot(valid && q == (uint32_t)kRadius);
+      if ((t & (kWave - 1)) == 0 && zmask) atomicAdd(&win[kRadius - wbase], (uint32_t)__popcll(zmask));
+      if (valid && q != (uint32_t)kRadius) {
+        if (q - wbase < (uint32_t)kWin) atomicAdd(&win[q - wbase], 1u);
+        else atomicAdd(&gh[q], 1u);
+      }
+    }
+    __syncthreads();
+  }
+  flush(cur);
+}
+
+// --------------------------------------------------------------- Huffman
+//
+// One workgroup of 1024 threads builds the code of one (field, predictor)
+// histogram.  Leaves are sorted by (weight, symbol) with a stable radix sort;
+// the two-queue Huffman merge (leaf taken first on equal weight, merged nodes
+// first-in first-out) runs in batches: with s the sum of the two lightest
+// nodes, every node of weight <= s precedes every node created from now on,
+// so the first 2j of them (j = floor(count/2)) pair up in order at once.  A
+// batch therefore reproduces exactly the sequential merge order.  Depths are
+// assigned batch by batch from the root; lengths above 24 halve every weight
+// ((w+1)/2) and rebuild; codes are canonical (RFC 1951, Sec. 3.2.2).
+
+constexpr int kHT = 1024;
+constexpr int kHW = kHT / kWave;
+
+struct HScratch {
+  uint16_t *a_sym; uint32_t *a_f;        // present symbols in symbol order
+  uint16_t *l_sym[2]; uint32_t *l_f[2];  // sort ping-pong
+  uint32_t *iw;                          // merged-node weights
+  uint32_t *parent;                      // 2n node parents
+  uint32_t *seqw, *seqid;                // merged order of one batch
+  uint32_t *batch_end;                   // merged-node count after each batch
+  uint8_t *depth;                        // 2n node depths
+  uint8_t *len_of;                       // 65536 lengths by symbol
+  uint16_t *c_sym;                       // canonical order
+};
+__host__ __device__ inline uint64_t hscratch_bytes() {
+  const uint64_t N = kNSyms;
+  return align8(2 * N) + align8(4 * N) + 2 * align8(2 * N) + 2 * align8(4 * N) + align8(4 * N) +
+         align8(8 * N) + 2 * align8(8 * N) + align8(4 * N) + align8(2 * N) + align8(N) + align8(2 * N) + 256;
+}
+__device__ inline HScratch hscratch_at(uint8_t *base) {
+  const uint64_t N = kNSyms;
+  HScratch h;
+  uint8_t *p = base;
+  h.a_sym = (uint16_t *)p; p += align8(2 * N);
+  h.a_f = (uint32_t *)p; p += align8(4 * N);
+  h.l_sym[0] = (uint16_t *)p; p += align8(2 * N);
+  h.l_sym[1] = (uint16_t *)p; p += align8(2 * N);
+  h.l_f[0] = (uint32_t *)p; p += align8(4 * N);
+  h.l_f[1] = (uint32_t *)p; p += align8(4 * N);
+  h.iw = (uint32_t *)p; p += align8(4 * N);
+  h.parent = (uint32_t *)p; p += align8(8 * N);
+  h.seqw = (uint32_t *)p; p += align8(8 * N);
+  h.seqid = (uint32_t *)p; p += align8(8 * N);
+  h.batch_end = (uint32_t *)p; p += align8(4 * N);
+  h.depth = (uint8_t *)p; p += align8(2 * N);
+  h.len_of = (uint8_t *)p; p += align8(N);
+  h.c_sym = (uint16_t *)p;
+  return h;
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const uint32_t l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// Stable counting sort of n (key, sym) pairs by digit (key >> shift) & mask,
+// nbits <= 8.  Wave w sorts segment w; order inside a segment and across
+// segments is kept.  keys_out may be null (then only syms move).
+__device__ void wg_split(const uint32_t *keys, const uint16_t *syms, uint32_t *keys_out, uint16_t *syms_out,
+                         const uint8_t *digit_of_sym, uint32_t n, int shift, int nbits, uint32_t *s_cnt,
+                         uint32_t *s_tot) {
+  const int t = threadIdx.x, w = t / kWave;
+  const uint32_t nd = 1u << nbits, mask = nd - 1;
+  const uint32_t seg = (n + kHW - 1) / kHW;
+  const uint32_t beg = min(n, seg * w), end = min(n, beg + seg);
+  for (uint32_t i = t; i < nd * kHW; i += kHT) s_cnt[i] = 0;
+  __syncthreads();
+  auto dig = [&](uint32_t i) -> uint32_t {
+    return digit_of_sym ? digit_of_sym[syms[i]] : (keys[i] >> shift) & mask;
+  };
+  for (uint32_t i = beg + lane_id(); i < end; i += kWave) atomicAdd(&s_cnt[dig(i) * kHW + w], 1u);
+  __syncthreads();
+  // exclusive scan over (digit, wave) in digit-major order
+  const uint32_t per = (nd * kHW + kHT - 1) / kHT;
+  uint32_t loc = 0;
+  for (uint32_t j = 0; j < per; j++) {
+    uint32_t i = t * per + j;
+    if (i < nd * kHW) loc += s_cnt[i];
+  }
+  uint32_t inc = wave_incl_scan(loc);
+  if (lane_id() == kWave - 1) s_tot[w] = inc;
+  __syncthreads();
+  uint32_t wpre = 0;
+  for (int i = 0; i < w; i++) wpre += s_tot[i];
+  uint32_t run = wpre + inc - loc;
+  for (uint32_t j = 0; j < per; j++) {
+    uint32_t i = t * per + j;
+    if (i < nd * kHW) { uint32_t v = s_cnt[i]; s_cnt[i] = run; run += v; }
+  }
+  __syncthreads();
+  for (uint32_t base = beg; base < end; base += kWave) {
+    const uint32_t i = base + lane_id();
+    const bool valid = i < end;
+    const uint32_t dg = valid ? dig(i) : 0u;
+    uint64_t m = __ballot(valid);
+    for (int bt = 0; bt < nbits; bt++) {
+      const uint64_t bb = __ballot(valid && ((dg >> bt) & 1u));
+      m &= ((dg >> bt) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(m & lanemask_lt());
+    const uint32_t cnt = __popcll(m);
+    uint32_t pos = 0;
+    if (valid) pos = s_cnt[dg * kHW + w] + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      if (keys_out) keys_out[pos] = keys[i];
+      syms_out[pos] = syms[i];
+      if (rank == cnt - 1) s_cnt[dg * kHW + w] += cnt;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+}
+
+// number of elements of a[0..n) that are <= v (a sorted)
+__device__ inline uint32_t count_le(const uint32_t *a, uint32_t n, uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) { uint32_t mid = (lo + hi) >> 1; if (a[mid] <= v) lo = mid + 1; else hi = mid; }
+  return lo;
+}
+__device__ inline uint32_t count_lt(const uint32_t *a, uint32_t n, uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) { uint32_t mid = (lo + hi) >> 1; if (a[mid] < v) lo = mid + 1; else hi = mid; }
+  return lo;
+}
+
+__global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int nf, uint8_t *scratch,
+                                              uint64_t slot_bytes) {
+  __shared__ uint32_t s_cnt[256 * kHW];
+  __shared__ uint32_t s_tot[kHW];
+  __shared__ uint32_t s_red[kHW];
+  __shared__ uint32_t s_n, s_maxf, s_maxlen, s_niter, s_lp, s_ip, s_ni, s_j, s_cL, s_cI, s_aL, s_done;
+  __shared__ uint32_t s_blc[32], s_first[32], s_base[32];
+  const int t = threadIdx.x, w = t / kWave;
+  HScratch H = hscratch_at(scratch + (uint64_t)blockIdx.x * slot_bytes);
+
+  for (int pair = blockIdx.x; pair < 3 * nf; pair += gridDim.x) {
+    const int f = pair / 3, slot = pair % 3;
+    const CField &c = F[f];
+    FState *st = c.st;
+    if ((uint32_t)slot >= c.nhist || st->status != 0 || st->is_const) continue;
+    const int k = slot_pred((int)c.policy, slot);
+    uint32_t *hist = c.hist + (uint64_t)slot * kNSyms;
+
+    // 1. present symbols in symbol order
+    {
+      constexpr int PER = kNSyms / kHT;
+      uint32_t cnt = 0, mf = 0;
+      for (int i = 0; i < PER; i++) { uint32_t v = hist[t * PER + i]; cnt += v != 0; mf = max(mf, v); }
+      uint32_t inc = wave_incl_scan(cnt);
+      mf = wave_max_u32(mf);
+      if (lane_id() == kWave - 1) { s_tot[w] = inc; s_red[w] = mf; }
+      __syncthreads();
+      uint32_t pre = 0;
+      for (int i = 0; i < w; i++) pre += s_tot[i];
+      uint32_t o = pre + inc - cnt;
+      for (int i = 0; i < PER; i++) {
+        uint32_t sym = t * PER + i;
+        uint32_t v = hist[sym];
+        if (v) { H.a_sym[o] = (uint16_t)sym; H.a_f[o] = v; o++; }
+      }
+      if (t == 0) {
+        uint32_t nn = 0, m2 = 0;
+        for (int i = 0; i < kHW; i++) { nn += s_tot[i]; m2 = max(m2, s_red[i]); }
+        s_n = nn; s_maxf = m2;
+      }
+      __syncthreads();
+    }
+    const uint32_t n = s_n;
+    if (n == 0) continue;
+
+    for (;;) {
+      uint32_t maxlen = 1;
+      if (n == 1) {
+        if (t == 0) { H.depth[0] = 1; H.l_sym[0][0] = H.a_sym[0]; }
+        __syncthreads();
+      } else {
+        // 2. leaves sorted by (weight, symbol): stable LSD radix on the weight
+        {
+          uint32_t mf = 0;  // weights may have been halved since step 1
+          for (uint32_t i = t; i < n; i += kHT) mf = max(mf, H.a_f[i]);
+          mf = wave_max_u32(mf);
+          if (lane_id() == 0) s_red[w] = mf;
+          __syncthreads();
+          if (t == 0) {
+            uint32_t m2 = 0;
+            for (int i = 0; i < kHW; i++) m2 = max(m2, s_red[i]);
+            s_maxf = m2;
+          }
+          __syncthreads();
+        }
+        int passes = 0;
+        {
+          uint32_t mf = s_maxf;
+          while (mf) { passes++; mf >>= 8; }
+          if (passes == 0) passes = 1;
+        }
+        const uint32_t *kin = H.a_f;
+        const uint16_t *sin = H.a_sym;
+        int pp = 0;
+        for (int ps = 0; ps < passes; ps++) {
+          wg_split(kin, sin, H.l_f[pp], H.l_sym[pp], nullptr, n, 8 * ps, 8, s_cnt, s_tot);
+          kin = H.l_f[pp];
+          sin = H.l_sym[pp];
+          pp ^= 1;
+        }
+        const uint32_t *Lw = kin;
+        const uint16_t *Ls = sin;
+
+        // 3. batched two-queue merge
+        if (t == 0) { s_lp = 0; s_ip = 0; s_ni = 0; s_niter = 0; }
+        __syncthreads();
+        for (;;) {
+          if (t == 0) {
+            const uint32_t lp = s_lp, ip = s_ip, ni = s_ni;
+            const uint32_t rem = (n - lp) + (ni - ip);
+            if (rem <= 1) {
+              s_done = 1;
+            } else {
+              s_done = 0;
+              uint32_t a = lp, bq = ip, wsum = 0;
+              for (int q = 0; q < 2; q++) {
+                bool leaf = a < n && (bq >= ni || Lw[a] <= H.iw[bq]);
+                if (leaf) wsum += Lw[a++]; else wsum += H.iw[bq++];
+              }
+              s_cL = count_le(Lw + lp, n - lp, wsum);
+              s_cI = count_le(H.iw + ip, ni - ip, wsum);
+              s_j = (s_cL + s_cI) / 2;
+              s_aL = 0;
+            }
+          }
+          __syncthreads();
+          if (s_done) break;
+          const uint32_t lp = s_lp, ip = s_ip, ni = s_ni, cL = s_cL, cI = s_cI, j = s_j;
+          for (uint32_t e = t; e < cL + cI; e += kHT) {
+            uint32_t wv, id, pos;
+            if (e < cL) {
+              wv = Lw[lp + e];
+              pos = e + count_lt(H.iw + ip, cI, wv);
+              id = lp + e;
+              if (pos < 2 * j) atomicAdd(&s_aL, 1u);
+            } else {
+              const uint32_t kk = e - cL;
+              wv = H.iw[ip + kk];
+              pos = kk + count_le(Lw + lp, cL, wv);
+              id = n + ip + kk;
+            }
+            if (pos < 2 * j) { H.seqw[pos] = wv; H.seqid[pos] = id; }
+          }
+          __syncthreads();
+          for (uint32_t i = t; i < j; i += kHT) {
+            H.iw[ni + i] = H.seqw[2 * i] + H.seqw[2 * i + 1];
+            H.parent[H.seqid[2 * i]] = n + ni + i;
+            H.parent[H.seqid[2 * i + 1]] = n + ni + i;
+          }
+          __syncthreads();
+          if (t == 0) {
+            s_lp = lp + s_aL;
+            s_ip = ip + 2 * j - s_aL;
+            s_ni = ni + j;
+            H.batch_end[s_niter] = ni + j;
+            s_niter = s_niter + 1;
+          }
+          __syncthreads();
+        }
+        // 4. depths from the root down, batch by batch
+        const uint32_t ni = s_ni, niter = s_niter;
+        const uint32_t root = n + ni - 1;
+        for (int it = (int)niter - 1; it >= 0; it--) {
+          const uint32_t lo = it ? H.batch_end[it - 1] : 0u, hi = H.batch_end[it];
+          for (uint32_t i = lo + t; i < hi; i += kHT) {
+            const uint32_t v = n + i;
+            H.depth[v] = v == root ? 0 : (uint8_t)(H.depth[H.parent[v]] + 1);
+          }
+          __syncthreads();
+        }
+        uint32_t ml = 0;
+        for (uint32_t i = t; i < n; i += kHT) {
+          uint8_t dd = (uint8_t)(H.depth[H.parent[i]] + 1);
+          H.depth[i] = dd;
+          ml = max(ml, (uint32_t)dd);
+        }
+        ml = wave_max_u32(ml);
+        if (lane_id() == 0) s_red[w] = ml;
+        __syncthreads();
+        if (t == 0) {
+          uint32_t m2 = 0;
+          for (int i = 0; i < kHW; i++) m2 = max(m2, s_red[i]);
+          s_maxlen = m2;
+        }
+        __syncthreads();
+        maxlen = s_maxlen;
+        if (maxlen > (uint32_t)kLMax) {
+          for (uint32_t i = t; i < n; i += kHT) H.a_f[i] = (H.a_f[i] + 1) >> 1;
+          __syncthreads();
+          continue;
+        }
+        // lengths by symbol (leaves are in sorted order in Ls)
+        for (uint32_t i = t; i < n; i += kHT) H.len_of[Ls[i]] = H.depth[i];
+        __syncthreads();
+      }
+      if (n == 1) {
+        if (t == 0) H.len_of[H.a_sym[0]] = 1;
+        __syncthreads();
+      }
+      // 5. canonical order = symbols stably sorted by length
+      wg_split(nullptr, H.a_sym, nullptr, H.c_sym, H.len_of, n, 0, 5, s_cnt, s_tot);
+      if (t < 32) s_blc[t] = 0;
+      __syncthreads();
+      for (uint32_t i = t; i < n; i += kHT) atomicAdd(&s_blc[H.len_of[H.a_sym[i]]], 1u);
+      __syncthreads();
+      if (t == 0) {
+        uint32_t code = 0, idx = 0, ml = 0;
+        for (int l = 1; l <= kLMax; l++) {
+          s_first[l] = code;
+          s_base[l] = idx;
+          code = (code + s_blc[l]) << 1;
+          idx += s_blc[l];
+          if (s_blc[l]) ml = (uint32_t)l;
+        }
+        s_maxlen = ml;
+      }
+      __syncthreads();
+      // 6. encoder table and staged codebook
+      uint32_t *enc = c.enc + (uint64_t)slot * kNSyms;
+      uint32_t *book = c.book + (uint64_t)slot * kBookWords;
+      uint16_t *bsym = reinterpret_cast<uint16_t *>(book + 32);
+      for (uint32_t i = t; i < n; i += kHT) {
+        const uint16_t sym = H.c_sym[i];
+        const uint32_t l = H.len_of[sym];
+        const uint32_t code = s_first[l] + (i - s_base[l]);
+        enc[sym] = code | (l << 24);
+        bsym[i] = sym;
+      }
+      if (t < 32) book[t] = (t >= 1 && t <= kLMax) ? s_blc[t] : 0u;
+      if (t == 0) { st->nsym[k] = n; st->maxlen[k] = s_maxlen; }
+      __syncthreads();
+      break;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- books
+
+// One workgroup per field: copy the staged codebooks into the stream, zero
+// their padding, and fix the payload offset.
+__global__ __launch_bounds__(kThreads) void k_books(const CField *__restrict__ F) {
+  const CField &c = F[blockIdx.x];
+  FState *st = c.st;
+  if (st->status != 0 || st->is_const) return;
+  const int t = threadIdx.x;
+  uint8_t *o = c.out;
+  uint64_t off = c.sec.books;
+  for (int k = 0; k < 3; k++) {
+    const uint32_t ns = st->nsym[k], ml = st->maxlen[k];
+    if (!ns) continue;
+    int slot = c.policy >= 2 ? k : 0;
+    const uint32_t *book = c.book + (uint64_t)slot * kBookWords;
+    const uint16_t *bsym = reinterpret_cast<const uint16_t *>(book + 32);
+    uint32_t *blc = reinterpret_cast<uint32_t *>(o + off);
+    for (uint32_t l = t; l < ml; l += kThreads) blc[l] = book[l + 1];
+    uint16_t *sy = reinterpret_cast<uint16_t *>(o + off + 4ull * ml);
+    for (uint32_t i = t; i < ns; i += kThreads) sy[i] = bsym[i];
+    const uint64_t end = off + 4ull * ml + 2ull * ns, nxt = align8(end);
+    if (t < 8 && end + t < nxt) o[end + t] = 0;
+    off = nxt;
+  }
+  if (t == 0) {
+    st->off_payload = off;
+    for (int k = 0; k < 3; k++) put32(o, H_NSYM + 4 * k, st->nsym[k]);
+    put32(o, H_MAXLEN, st->maxlen[0] | (st->maxlen[1] << 8) | (st->maxlen[2] << 16));
+    put64(o, H_OFF_PAYLOAD, off);
+  }
+}
+
+// ------------------------------------------------------------------ pack
+
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagPre = 2ull << 62, kValMask = (1ull << 62) - 1;
+
+template <int E>
+__global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F, int nf,
+                                                   const uint64_t *__restrict__ fb0, uint64_t total, GCtl *gc) {
+  constexpr int S = E * kThreads;
+  constexpr int CWMAX = S * kLMax / 32;
+  __shared__ uint32_t s_words[CWMAX];
+  __shared__ int32_t s_tail[3 * kThreads];
+  __shared__ int32_t s_p0;
+  __shared__ uint32_t s_g;
+  __shared__ unsigned long long s_wtot[kThreads / kWave];
+  __shared__ unsigned long long s_prefix;
+  const int t = threadIdx.x, w = t / kWave;
+
+  for (;;) {
+    if (t == 0) s_g = atomicAdd(&gc->ticket, 1u);
+    __syncthreads();
+    const uint64_t g = s_g;
+    __syncthreads();
+    if (g >= total) break;
+    const int f = find_field(fb0, nf, g);
+    const CField &c = F[f];
+    FState *st = c.st;
+    if (st->status != 0 || st->is_const) continue;
+    const uint64_t b = g - c.gblock0;
+    const uint64_t i0 = b * S;
+    const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
+    int32_t d[E], pv[3], p0;
+    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
+    const int pred = c.policy >= 2 ? (int)c.out[c.sec.pred + b] : (int)c.policy;
+    const int slot = c.policy >= 2 ? pred : 0;
+    const uint32_t *enc = c.enc + (uint64_t)slot * kNSyms;
+
+    uint32_t cw[E];
+    int32_t rr[E];
+    uint32_t bits = 0, nesc = 0;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const bool valid = (uint32_t)t * E + e < len;
+      int32_t r = residual_at<E>(d, pv, e, pred);
+      uint32_t q = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
+      rr[e] = r;
+      cw[e] = valid ? enc[q] : 0u;
+      bits += cw[e] >> 24;
+      nesc += (valid && q == 0u) ? 1u : 0u;
+    }
+    // block exclusive scan of (bits, escapes)
+    const unsigned long long mine = (unsigned long long)bits | ((unsigned long long)nesc << 32);
+    const unsigned long long inc = wave_incl_scan(mine);
+    if (lane_id() == kWave - 1) s_wtot[w] = inc;
+    __syncthreads();
+    unsigned long long pre = 0, tot = 0;
+    for (int i = 0; i < kThreads / kWave; i++) {
+      if (i < w) pre += s_wtot[i];
+      tot += s_wtot[i];
+    }
+    const unsigned long long ex = pre + inc - mine;
+    const uint32_t bit0 = (uint32_t)ex, esc0 = (uint32_t)(ex >> 32);
+    const uint32_t tbits = (uint32_t)tot, tesc = (uint32_t)(tot >> 32);
+    const uint32_t cwn = (tbits + 31) / 32;
+    const uint64_t words = (uint64_t)cwn + tesc;
+
+    // decoupled look-back over the field's earlier blocks
+    if (t == 0) {
+      uint64_t P = 0;
+      if (b == 0) {
+        st_release_u64(&c.lbflag[b], kFlagPre | words);
+      } else {
+        st_release_u64(&c.lbflag[b], kFlagAgg | words);
+        int64_t j = (int64_t)b - 1;
+        for (;;) {
+          uint64_t v = ld_acquire_u64(&c.lbflag[j]);
+          if (v == 0) { __builtin_amdgcn_s_sleep(1); continue; }
+          P += v & kValMask;
+          if ((v >> 62) == 2) break;
+          j--;
+        }
+        st_release_u64(&c.lbflag[b], kFlagPre | (P + words));
+      }
+      s_prefix = P;
+    }
+    for (uint32_t i = t; i < cwn; i += kThreads) s_words[i] = 0u;
+    __syncthreads();
+    // MSB-first packing of this thread's codewords
+    uint32_t o = bit0;
+#pragma unroll
+    for (int e = 0; e < E; e++) {
+      const uint32_t l = cw[e] >> 24, code = cw[e] & 0xffffffu;
+      if (l) {
+        const uint32_t wi = o >> 5, sh = o & 31u;
+        if (sh + l <= 32u) {
+          atomicOr(&s_words[wi], code << (32u - sh - l));
+        } else {
+          const uint32_t over = sh + l - 32u;
+          atomicOr(&s_words[wi], code >> over);
+          atomicOr(&s_words[wi + 1], code << (32u - over));
+        }
+        o += l;
+      }
+    }
+    __syncthreads();
+    const uint64_t P = s_prefix;
+    const uint64_t wbase = st->off_payload / 4 + P;
+    const bool fits = (wbase + words) * 4 <= c.out_cap;
+    uint32_t *ow = reinterpret_cast<uint32_t *>(c.out);
+    if (fits) {
+      for (uint32_t i = t; i < cwn; i += kThreads) ow[wbase + i] = s_words[i];
+      if (nesc) {
+        uint32_t ei = esc0;
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+          const bool valid = (uint32_t)t * E + e < len;
+          if (valid && !(rr[e] > -kRadius && rr[e] < kRadius)) ow[wbase + cwn + ei++] = (uint32_t)rr[e];
+        }
+      }
+    } else if (t == 0) {
+      st->status = SZNB_ENOSPC;
+    }
+    if (t == 0) {
+      reinterpret_cast<uint16_t *>(c.out + c.sec.cwords)[b] = (uint16_t)cwn;
+      reinterpret_cast<uint16_t *>(c.out + c.sec.nesc)[b] = (uint16_t)tesc;
+      if (b + 1 == c.nblocks) st->payload_words = P + words;
+      __threadfence();
+      const uint32_t done = atomicAdd(&st->blocks_done, 1u);
+      if (done + 1 == c.nblocks) {
+        __threadfence();
+        const uint64_t pw = __hip_atomic_load(&st->payload_words, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t tb = st->off_payload + 4 * pw;
+        const int status = __hip_atomic_load(&st->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (status != 0 || tb > c.out_cap) {
+          st->status = SZNB_ENOSPC;
+          if (c.out_len) *c.out_len = 0;
+        } else {
+          put64(c.out, H_PWORDS, pw);
+          put64(c.out, H_TOTAL, tb);
+          if (c.out_len) *c.out_len = tb;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// explicit instantiations (block sizes 1K..16K)
+#define SZNB_INST(E)                                                                                        \
+  template __global__ void k_quant<E>(const CField *, int, const uint64_t *, uint64_t, const uint32_t *); \
+  template __global__ void k_pack<E>(const CField *, int, const uint64_t *, uint64_t, GCtl *);
+SZNB_INST(4)
+SZNB_INST(8)
+SZNB_INST(16)
+SZNB_INST(32)
+SZNB_INST(64)
+
+}  // namespace sznb
+
+namespace sznb {
+uint64_t hscratch_bytes_host() { return hscratch_bytes(); }
+}  // namespace sznb

@@ -1,0 +1,498 @@
+// Decompression kernels of the sznb library (gfx950, wave64).
+//
+//   d_prep     header validation, block word offsets, blocks grouped by
+//              predictor (one workgroup per stream)
+//   d_tables   canonical decode tables per (stream, predictor): a 4096-entry
+//              first-level table and per-length limits for longer codes
+//   d_tasks    task prefix over (stream, predictor) groups
+//   d_decode   one wave per block: self-synchronising parallel Huffman decode
+//              of the block's bits, escapes, inverse prediction by a wave scan
+//              of affine prefix maps, reconstruction x~ = fl32(fma(p, step, mn))
+//   d_const    constant streams
+//
+// Self-synchronising decode: the block's code bits are cut into 64 word-
+// aligned ranges, one per lane.  Each lane first decodes from the start of
+// its range as if a codeword began there, marking the positions it decodes
+// in an LDS bitmap.  A lane's true start is where its left neighbour's
+// decoding leaves its range; a lane whose guess was wrong decodes again from
+// the true start until it lands on a marked position -- from there on its
+// first pass was right (prefix codes resynchronise) -- and the symbols it
+// owns are the ones decoded plus the marks counted after that point.  The
+// correction repeats until no start moves (at most 64 rounds, usually one).
+#include "sznb_internal.h"
+
+namespace sznb {
+
+__device__ inline uint32_t rd32(const uint8_t *p, uint64_t off) {
+  return (uint32_t)p[off] | ((uint32_t)p[off + 1] << 8) | ((uint32_t)p[off + 2] << 16) | ((uint32_t)p[off + 3] << 24);
+}
+__device__ inline uint64_t rd64(const uint8_t *p, uint64_t off) {
+  return (uint64_t)rd32(p, off) | ((uint64_t)rd32(p, off + 4) << 32);
+}
+__device__ inline uint16_t rd16(const uint8_t *p, uint64_t off) {
+  return (uint16_t)(p[off] | (p[off + 1] << 8));
+}
+
+// ---------------------------------------------------------------- prep
+
+__global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D) {
+  const DField &df = D[blockIdx.x];
+  DState *st = df.st;
+  const uint8_t *in = df.in;
+  const int t = threadIdx.x;
+  __shared__ int s_bad;
+  __shared__ uint32_t s_tot[kThreads / kWave][4];
+  if (t == 0) {
+    int bad = 0;
+    st->status = 0;
+    st->is_const = 0;
+    if (df.in_len < (uint64_t)kHdr || rd32(in, H_MAGIC) != kMagic || rd16(in, H_VERSION) != 1) bad = 1;
+    uint32_t policy = 0, flags = 0, S = 0, nb = 0;
+    uint64_t n = 0, total = 0;
+    if (!bad) {
+      policy = in[H_POLICY];
+      flags = in[H_FLAGS];
+      n = rd64(in, H_N);
+      S = rd32(in, H_S);
+      nb = rd32(in, H_NB);
+      total = rd64(in, H_TOTAL);
+      if (policy > 3 || n != df.n || total > df.in_len || S < 1024 || S > 16384 || (S & (S - 1))) bad = 1;
+    }
+    st->policy = policy; st->S = S; st->n = n;
+    st->mn = __uint_as_float(bad ? 0u : rd32(in, H_MN));
+    if (!bad && (flags & 1u)) {
+      st->is_const = 1;
+      st->nblocks = 0;
+    } else if (!bad) {
+      const uint64_t nbx = (n + S - 1) / S;
+      if (nb != nbx || nb > df.nblocks_max || n == 0) bad = 1;
+      Sections sec = sections_of(nb, (int)policy);
+      st->step = __longlong_as_double((long long)rd64(in, H_STEP));
+      st->off_pred = rd64(in, H_OFF_PRED);
+      st->off_pfirst = rd64(in, H_OFF_PFIRST);
+      st->off_cwords = rd64(in, H_OFF_CWORDS);
+      st->off_nesc = rd64(in, H_OFF_NESC);
+      const uint64_t off_books = rd64(in, H_OFF_BOOKS);
+      st->off_payload = rd64(in, H_OFF_PAYLOAD);
+      st->payload_words = rd64(in, H_PWORDS);
+      if (st->off_pred != sec.pred || st->off_pfirst != sec.pfirst || st->off_cwords != sec.cwords ||
+          st->off_nesc != sec.nesc || off_books != sec.books)
+        bad = 1;
+      uint64_t o = off_books;
+      for (int k = 0; k < 3; k++) {
+        const uint32_t ns = rd32(in, H_NSYM + 4 * k), ml = in[H_MAXLEN + k];
+        st->nsym[k] = ns;
+        st->maxlen[k] = ml;
+        st->book_off[k] = o;
+        if ((ns == 0) != (ml == 0) || ns > (uint32_t)kNSyms || ml > (uint32_t)kLMax) bad = 1;
+        o += book_bytes(ns, ml);
+      }
+      if (policy < 2 && st->nsym[policy] == 0) bad = 1;
+      if (o != st->off_payload || st->off_payload + 4 * st->payload_words != total) bad = 1;
+      st->nblocks = bad ? 0 : nb;
+    }
+    s_bad = bad;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (t == 0) { st->status = SZNB_ECORRUPT; st->nblocks = 0; }
+    return;
+  }
+  if (st->is_const) return;
+  // block word offsets and predictor groups
+  const uint32_t nb = st->nblocks, policy = st->policy, S = st->S;
+  const uint32_t cwmax = S * kLMax / 32;
+  const uint32_t per = (nb + kThreads - 1) / kThreads;
+  const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
+  uint32_t words = 0, cnt[3] = {0, 0, 0}, bad = 0;
+  for (uint32_t b = lo; b < hi; b++) {
+    const uint32_t cw = rd16(in, st->off_cwords + 2ull * b), ne = rd16(in, st->off_nesc + 2ull * b);
+    const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
+    const uint32_t blen = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
+    if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) bad = 1;
+    else cnt[k]++;
+    words += cw + ne;
+  }
+  // workgroup exclusive scans of (words, cnt0, cnt1, cnt2)
+  uint32_t v[4] = {words, cnt[0], cnt[1], cnt[2]}, ex[4], tot[4];
+  const int w = t / kWave;
+  for (int i = 0; i < 4; i++) {
+    uint32_t inc = wave_incl_scan(v[i]);
+    ex[i] = inc - v[i];
+    if (lane_id() == kWave - 1) s_tot[w][i] = inc;
+  }
+  bad = wave_max_u32(bad);
+  if (lane_id() == 0 && bad) s_bad = 1;
+  __syncthreads();
+  for (int i = 0; i < 4; i++) {
+    tot[i] = 0;
+    for (int j = 0; j < kThreads / kWave; j++) {
+      if (j < w) ex[i] += s_tot[j][i];
+      tot[i] += s_tot[j][i];
+    }
+  }
+  if (s_bad || tot[0] != st->payload_words) {
+    if (t == 0) { st->status = SZNB_ECORRUPT; st->nblocks = 0; }
+    return;
+  }
+  uint32_t gstart[3] = {0, tot[1], tot[1] + tot[2]};
+  uint32_t run = ex[0], gpos[3] = {gstart[0] + ex[1], gstart[1] + ex[2], gstart[2] + ex[3]};
+  for (uint32_t b = lo; b < hi; b++) {
+    df.boff[b] = run;
+    run += rd16(in, st->off_cwords + 2ull * b) + rd16(in, st->off_nesc + 2ull * b);
+    const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
+    df.order[gpos[k]++] = b;
+  }
+  if (t == 0) {
+    for (int k = 0; k < 3; k++) { st->grp_count[k] = tot[1 + k]; st->grp_start[k] = gstart[k]; }
+  }
+}
+
+// --------------------------------------------------------------- tables
+
+__global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ D) {
+  const DField &df = D[blockIdx.x / 3];
+  const int k = blockIdx.x % 3;
+  DState *st = df.st;
+  const int t = threadIdx.x;
+  __shared__ uint32_t s_cnt[32], s_first[32], s_base[32];
+  __shared__ uint64_t s_limit[32];
+  __shared__ int s_ok;
+  if (st->status != 0 || st->is_const || st->nsym[k] == 0) return;
+  const uint8_t *in = df.in;
+  const uint32_t ns = st->nsym[k], ml = st->maxlen[k];
+  const uint64_t bo = st->book_off[k];
+  if (t == 0) {
+    uint32_t tot = 0, code = 0, idx = 0;
+    int ok = 1;
+    for (int l = 0; l < 32; l++) { s_cnt[l] = 0; s_first[l] = 0; s_base[l] = 0; s_limit[l] = 0; }
+    for (uint32_t l = 1; l <= ml; l++) { s_cnt[l] = rd32(in, bo + 4ull * (l - 1)); tot += s_cnt[l]; }
+    if (tot != ns || s_cnt[ml] == 0) ok = 0;
+    for (uint32_t l = 1; l <= ml && ok; l++) {
+      s_first[l] = code;
+      s_base[l] = idx;
+      if ((uint64_t)code + s_cnt[l] > (1ull << l)) ok = 0;  // not a prefix code
+      s_limit[l] = ((uint64_t)code + s_cnt[l]) << (32 - l);
+      code = (code + s_cnt[l]) << 1;
+      idx += s_cnt[l];
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  if (!s_ok) {
+    if (t == 0) st->status = SZNB_ECORRUPT;
+    return;
+  }
+  uint16_t *syms = df.syms + (uint64_t)k * kNSyms;
+  const uint64_t so = bo + 4ull * ml;
+  for (uint32_t i = t; i < ns; i += kThreads) syms[i] = rd16(in, so + 2ull * i);
+  __syncthreads();
+  uint32_t *lut = df.lut + (uint64_t)k * (1u << kLutBits);
+  for (uint32_t e = t; e < (1u << kLutBits); e += kThreads) {
+    const uint64_t win = (uint64_t)e << (32 - kLutBits);
+    uint32_t len = 1;
+    for (uint32_t l = 1; l <= ml; l++) len += s_limit[l] <= win;
+    uint32_t ent;
+    if (len > ml) ent = kLutInvalid | 0xffffu | (1u << 16);
+    else if (len > (uint32_t)kLutBits) ent = kLutLong;
+    else {
+      const uint32_t code = (uint32_t)(win >> (32 - len));
+      ent = (uint32_t)syms[s_base[len] + (code - s_first[len])] | (len << 16);
+    }
+    lut[e] = ent;
+  }
+  uint32_t *slow = df.slow + (uint64_t)k * kSlowWords;
+  if (t < 32) {
+    slow[t] = s_first[t];
+    slow[32 + t] = s_base[t];
+    slow[64 + 2 * t] = (uint32_t)s_limit[t];
+    slow[64 + 2 * t + 1] = (uint32_t)(s_limit[t] >> 32);
+  }
+}
+
+// ---------------------------------------------------------------- tasks
+
+// tbase[p] for p = 3 f + k: first decode task of (stream f, predictor k); a
+// task is up to `dw` consecutive blocks of one group.
+__global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t dw,
+                                                    uint32_t *tbase) {
+  __shared__ uint32_t s_tot[kThreads / kWave];
+  const int t = threadIdx.x, w = t / kWave;
+  const int np = 3 * nf;
+  const int per = (np + kThreads - 1) / kThreads;
+  uint32_t loc = 0;
+  for (int j = 0; j < per; j++) {
+    const int p = t * per + j;
+    if (p < np) {
+      const DState *st = D[p / 3].st;
+      if (st->status == 0 && !st->is_const) loc += (st->grp_count[p % 3] + dw - 1) / dw;
+    }
+  }
+  const uint32_t inc = wave_incl_scan(loc);
+  if (lane_id() == kWave - 1) s_tot[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - loc;
+  for (int i = 0; i < w; i++) run += s_tot[i];
+  for (int j = 0; j < per; j++) {
+    const int p = t * per + j;
+    if (p < np) {
+      tbase[p] = run;
+      const DState *st = D[p / 3].st;
+      if (st->status == 0 && !st->is_const) run += (st->grp_count[p % 3] + dw - 1) / dw;
+    }
+  }
+  if (t == kThreads - 1) tbase[np] = run;
+}
+
+__global__ void d_const(const DField *__restrict__ D, int nf) {
+  for (int f = 0; f < nf; f++) {
+    const DField &df = D[f];
+    const DState *st = df.st;
+    if (st->status != 0 || !st->is_const) continue;
+    const float v = st->mn;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < st->n; i += (uint64_t)gridDim.x * blockDim.x)
+      df.out[i] = v;
+  }
+}
+
+// --------------------------------------------------------------- decode
+
+struct DecTab {
+  const uint32_t *lut;     // LDS
+  const uint32_t *first;   // LDS
+  const uint32_t *base;    // LDS
+  const uint32_t *limit;   // LDS (lo, hi pairs)
+  const uint16_t *syms;    // global
+  uint32_t maxlen;
+};
+
+// next 32 bits of the block's code region at bit `pos` (zeros past the end)
+__device__ inline uint32_t window_at(const uint32_t *wp, uint32_t cw, uint32_t pos) {
+  const uint32_t wi = pos >> 5, sh = pos & 31u;
+  const uint32_t w0 = wi < cw ? wp[wi] : 0u;
+  const uint32_t w1 = wi + 1 < cw ? wp[wi + 1] : 0u;
+  return sh ? (w0 << sh) | (w1 >> (32u - sh)) : w0;
+}
+
+// decode one codeword from a 32-bit window: returns sym | len << 16, or an
+// invalid marker with length 1
+__device__ inline uint32_t decode_one(const DecTab &T, uint32_t win) {
+  uint32_t e = T.lut[win >> (32 - kLutBits)];
+  if (e & kLutLong) {
+    uint32_t len = kLutBits + 1;
+    while (len <= T.maxlen) {
+      const uint64_t lim = (uint64_t)T.limit[2 * len] | ((uint64_t)T.limit[2 * len + 1] << 32);
+      if ((uint64_t)win < lim) break;
+      len++;
+    }
+    if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
+    const uint32_t code = win >> (32 - len);
+    return (uint32_t)T.syms[T.base[len] + (code - T.first[len])] | (len << 16);
+  }
+  return e;
+}
+
+// one wave decodes block b of a stream into LDS floats and stores them
+__device__ void decode_block(const DField &df, const DState *st, const DecTab &T, uint32_t b, uint8_t *reg,
+                             int *bad_flag) {
+  const uint32_t l = lane_id();
+  const uint8_t *in = df.in;
+  const uint32_t S = st->S;
+  const uint32_t E2 = S / kWave;
+  const uint32_t len = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
+  const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
+  const uint32_t ne = rd16(in, st->off_nesc + 2ull * b);
+  const uint32_t k = st->policy >= 2 ? in[st->off_pred + b] : st->policy;
+  const int32_t p0 = (int32_t)rd32(in, st->off_pfirst + 4ull * b);
+  const uint32_t *wp = reinterpret_cast<const uint32_t *>(in + st->off_payload) + df.boff[b];
+  uint32_t *bm = reinterpret_cast<uint32_t *>(reg);
+
+  // ranges
+  const uint32_t s = 32u * ((l * cw) / kWave), e = 32u * (((l + 1) * cw) / kWave);
+  for (uint32_t i = s >> 5; i < (e >> 5); i++) bm[i] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  // phase 1: speculative decode of the own range
+  uint32_t pos = s, cnt = 0;
+  while (pos < e) {
+    const uint32_t r = decode_one(T, window_at(wp, cw, pos));
+    atomicOr(&bm[pos >> 5], 1u << (pos & 31u));
+    pos += (r >> 16) & 31u;
+    cnt++;
+  }
+  // exit1: where the first-pass path leaves the range (the true exit once a
+  // corrected path lands on a first-pass mark)
+  uint32_t start = s, exit1 = pos, exitp = pos;
+  __builtin_amdgcn_wave_barrier();
+  // phase 2: move wrong starts to the true ones
+  for (int it = 0; it <= kWave; it++) {
+    uint32_t tin = __shfl_up(exitp, 1, kWave);
+    if (l == 0) tin = 0;
+    const bool changed = tin != start;
+    if (!__ballot(changed)) break;
+    if (changed) {
+      uint32_t p = tin, c2 = 0;
+      bool synced = false;
+      while (p < e) {
+        if ((bm[p >> 5] >> (p & 31u)) & 1u) { synced = true; break; }
+        const uint32_t r = decode_one(T, window_at(wp, cw, p));
+        p += (r >> 16) & 31u;
+        c2++;
+      }
+      if (synced) {
+        uint32_t pc = __popc(bm[p >> 5] & (~0u << (p & 31u)));
+        for (uint32_t i = (p >> 5) + 1; i < (e >> 5); i++) pc += __popc(bm[i]);
+        cnt = c2 + pc;
+        exitp = exit1;
+      } else {
+        cnt = c2;
+        exitp = p;
+      }
+      start = tin;
+    }
+  }
+  const uint32_t total = wave_sum(cnt);
+  if (total < len) { if (l == 0) *bad_flag = 1; return; }
+  const uint32_t o = wave_incl_scan(cnt) - cnt;
+  __builtin_amdgcn_wave_barrier();
+  // phase 3: emit the owned symbols into the lane-chunk layout of reg
+  uint16_t *q16 = reinterpret_cast<uint16_t *>(reg);
+  auto qidx = [&](uint32_t el) -> uint32_t { return (el / E2) * 2u * E2 + E2 + (el % E2); };
+  uint32_t invalid = 0;
+  {
+    uint32_t p = start, i = o;
+    while (p < e && i < len) {
+      const uint32_t r = decode_one(T, window_at(wp, cw, p));
+      if (r & kLutInvalid) invalid = 1;
+      q16[qidx(i)] = (uint16_t)(r & 0xffffu);
+      p += (r >> 16) & 31u;
+      i++;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // phase 4: escapes, inverse prediction, reconstruction
+  const uint32_t c0 = l * E2, c1 = min(len, c0 + E2);
+  const uint32_t m = c1 > c0 ? c1 - c0 : 0u;
+  uint32_t ebase = 0;
+  if (ne) {
+    uint32_t ec = 0;
+    for (uint32_t j = c0; j < c1; j++) ec += q16[qidx(j)] == 0;
+    const uint32_t etot = wave_sum(ec);
+    if (etot != ne) invalid = 1;
+    ebase = wave_incl_scan(ec) - ec;
+  }
+  if (l == 0 && len && q16[qidx(0)] != (uint16_t)kRadius) invalid = 1;
+  const uint32_t *esc = wp + cw;
+  // pass A: affine map of the lane's chunk (residual fed at level k)
+  uint32_t s0 = 0, s1 = 0, s2 = 0;
+  {
+    uint32_t ei = ebase;
+    for (uint32_t j = c0; j < c1; j++) {
+      const uint32_t q = q16[qidx(j)];
+      uint32_t r;
+      if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
+      if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
+      else if (k == 1) { s1 += r; s0 += s1; }
+      else s0 += r;
+    }
+  }
+  // wave exclusive scan of chunk maps (m, R1, R2, R3) = (m, s2, s1, s0)
+  uint32_t tm = m, R1 = s2, R2 = s1, R3 = s0;
+#pragma unroll
+  for (int dd = 1; dd < kWave; dd <<= 1) {
+    const uint32_t am = __shfl_up(tm, dd, kWave), a1 = __shfl_up(R1, dd, kWave);
+    const uint32_t a2 = __shfl_up(R2, dd, kWave), a3 = __shfl_up(R3, dd, kWave);
+    if (l >= (uint32_t)dd) {
+      const uint32_t mb = tm, T2 = (uint32_t)(((uint64_t)mb * (mb + 1)) >> 1);
+      R3 = a3 + mb * a2 + T2 * a1 + R3;
+      R2 = a2 + mb * a1 + R2;
+      R1 = a1 + R1;
+      tm = am + mb;
+    }
+  }
+  uint32_t x1 = __shfl_up(R1, 1, kWave), x2 = __shfl_up(R2, 1, kWave), x3 = __shfl_up(R3, 1, kWave);
+  if (l == 0) { x1 = 0; x2 = 0; x3 = 0; }
+  // pass B: states from the prefix, reconstructed floats written in place
+  {
+    s2 = x1; s1 = x2; s0 = x3;
+    uint32_t ei = ebase;
+    float *fo = reinterpret_cast<float *>(reg);
+    const double step = st->step, mn = (double)st->mn;
+    for (uint32_t j = c0; j < c1; j++) {
+      const uint32_t q = q16[qidx(j)];
+      uint32_t r;
+      if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
+      if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
+      else if (k == 1) { s1 += r; s0 += s1; }
+      else s0 += r;
+      const int32_t p = (int32_t)((uint32_t)p0 + s0);
+      fo[j] = (float)fma((double)p, step, mn);
+    }
+  }
+  if (__ballot(invalid)) { if (l == 0) *bad_flag = 1; }
+  __builtin_amdgcn_wave_barrier();
+  // coalesced store of the block
+  const float *fo = reinterpret_cast<const float *>(reg);
+  float *out = df.out + (uint64_t)b * S;
+  for (uint32_t j = 4 * l; j < len; j += 4 * kWave) {
+    if (j + 4 <= len) {
+      *reinterpret_cast<float4 *>(out + j) = *reinterpret_cast<const float4 *>(fo + j);
+    } else {
+      for (uint32_t i = j; i < len; i++) out[i] = fo[i];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// dw waves per workgroup; dynamic LDS: lut | slow | dw regions of 4*Smax bytes
+__global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
+                         uint32_t dw, uint32_t smax) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *s_slow = s_lut + (1u << kLutBits);
+  uint8_t *regs = reinterpret_cast<uint8_t *>(s_slow + kSlowWords);
+  __shared__ int s_bad;
+  const int t = threadIdx.x;
+  const uint32_t w = t / kWave;
+  const int np = 3 * nf;
+  const uint32_t T = tbase[np];
+  const uint32_t G = gridDim.x;
+  const uint32_t t0 = (uint32_t)(((uint64_t)T * blockIdx.x) / G), t1 = (uint32_t)(((uint64_t)T * (blockIdx.x + 1)) / G);
+  int cur = -1;
+  for (uint32_t task = t0; task < t1; task++) {
+    // pair of this task
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (tbase[mid] <= task) lo = mid; else hi = mid - 1;
+    }
+    const int pair = lo, f = pair / 3, k = pair % 3;
+    const DField &df = D[f];
+    const DState *st = df.st;
+    if (pair != cur) {
+      __syncthreads();
+      const uint32_t *gl = df.lut + (uint64_t)k * (1u << kLutBits);
+      for (uint32_t i = t; i < (1u << kLutBits); i += blockDim.x) s_lut[i] = gl[i];
+      const uint32_t *gs = df.slow + (uint64_t)k * kSlowWords;
+      for (uint32_t i = t; i < (uint32_t)kSlowWords; i += blockDim.x) s_slow[i] = gs[i];
+      if (t == 0) s_bad = 0;
+      __syncthreads();
+      cur = pair;
+    }
+    DecTab T2;
+    T2.lut = s_lut;
+    T2.first = s_slow;
+    T2.base = s_slow + 32;
+    T2.limit = s_slow + 64;
+    T2.syms = df.syms + (uint64_t)k * kNSyms;
+    T2.maxlen = st->maxlen[k];
+    const uint32_t idx = (task - tbase[pair]) * dw + w;
+    if (idx < st->grp_count[k]) {
+      const uint32_t b = df.order[st->grp_start[k] + idx];
+      int bad = 0;
+      decode_block(df, st, T2, b, regs + (uint64_t)w * 4u * smax, &bad);
+      if (bad && lane_id() == 0) atomicCAS((int *)&df.st->status, 0, SZNB_ECORRUPT);
+    }
+  }
+}
+
+}  // namespace sznb

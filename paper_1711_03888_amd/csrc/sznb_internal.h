@@ -1,0 +1,198 @@
+// Internal definitions of the sznb HIP library (device structs, stream
+// layout constants, wave-level primitives).  gfx950 only: wave64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sznb.h"
+
+namespace sznb {
+
+constexpr int kRadius = 32768;       // 65536 quantization intervals, code 0 = escape
+constexpr int kNSyms = 65536;
+constexpr int kLMax = 24;            // Huffman code lengths are limited to 24 bits
+constexpr int64_t kPMax = 1 << 27;   // largest lattice span accepted
+constexpr int kHdr = 128;
+constexpr int kLutBits = 12;         // first-level decode table
+constexpr int kNClass = 33;          // residual classes of the block-cost estimate
+constexpr int kThreads = 256;        // workgroup size of the per-block kernels
+constexpr int kWave = 64;
+
+// header byte offsets
+enum : int {
+  H_MAGIC = 0, H_VERSION = 4, H_POLICY = 6, H_FLAGS = 7, H_N = 8, H_S = 16, H_NB = 20,
+  H_MN = 24, H_MX = 28, H_EBABS = 32, H_STEP = 40, H_NSYM = 48, H_MAXLEN = 60,
+  H_PWORDS = 64, H_TOTAL = 72, H_OFF_PRED = 80, H_OFF_PFIRST = 88, H_OFF_CWORDS = 96,
+  H_OFF_NESC = 104, H_OFF_BOOKS = 112, H_OFF_PAYLOAD = 120
+};
+constexpr uint32_t kMagic = 0x424E5A53u;  // "SZNB"
+
+__host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~uint64_t(7); }
+
+// Section offsets that depend only on the block count and the policy.
+struct Sections {
+  uint64_t pred, pfirst, cwords, nesc, books;
+};
+__host__ __device__ inline Sections sections_of(uint64_t nb, int policy) {
+  Sections s;
+  uint64_t o = kHdr;
+  s.pred = 0;
+  if (policy >= 2) { s.pred = o; o = align8(o + nb); }
+  s.pfirst = o; o = align8(o + 4 * nb);
+  s.cwords = o; o = align8(o + 2 * nb);
+  s.nesc = o; o = align8(o + 2 * nb);
+  s.books = o;
+  return s;
+}
+__host__ __device__ inline uint64_t book_bytes(uint32_t nsym, uint32_t maxlen) {
+  return nsym ? align8(4ull * maxlen + 2ull * nsym) : 0;
+}
+
+// ---------------------------------------------------------------- compress
+
+// per-field state written by the device
+struct alignas(64) FState {
+  int32_t status;
+  uint32_t is_const;
+  float mn, mx;
+  double R, eb_abs, step, inv;
+  int64_t P;
+  uint32_t nsym[3];
+  uint32_t maxlen[3];
+  uint64_t off_payload;
+  uint64_t payload_words;
+  uint32_t blocks_done;
+  uint32_t pad0;
+};
+
+// per-field descriptor written by the host
+struct alignas(16) CField {
+  const float *x;
+  uint64_t n;
+  double eb;
+  uint8_t *out;
+  uint64_t out_cap;
+  uint64_t *out_len;      // device word receiving the stream length
+  uint32_t policy, eb_rel, S, log2S;
+  uint32_t nblocks, nhist;
+  uint64_t gblock0;       // first global block index of this field
+  Sections sec;
+  FState *st;
+  uint32_t *blkstat;      // 3 words per block: min key, max key, non-finite flag
+  uint32_t *hist;         // nhist x 65536 code counts
+  uint32_t *enc;          // nhist x 65536 codewords: code | len << 24
+  uint32_t *book;         // nhist x (32 bl_count words + 32768 words of u16 symbols)
+  uint64_t *lbflag;       // decoupled look-back words, one per block
+};
+constexpr int kBookWords = 32 + kNSyms / 2;
+
+struct alignas(64) GCtl {
+  uint32_t ticket;        // block tickets of the pack kernel
+  uint32_t pad[15];
+};
+
+// predictor that histogram slot s of a field codes
+__host__ __device__ inline int slot_pred(int policy, int s) { return policy >= 2 ? s : policy; }
+
+// ------------------------------------------------------------- decompress
+
+struct alignas(64) DState {
+  int32_t status;
+  uint32_t is_const;
+  uint32_t policy, S, nblocks, pad1;
+  uint64_t n;
+  float mn;
+  uint32_t pad2;
+  double step;
+  uint64_t off_pred, off_pfirst, off_cwords, off_nesc, off_payload, payload_words;
+  uint32_t nsym[3], maxlen[3];
+  uint64_t book_off[3];
+  uint32_t grp_count[3];  // blocks per predictor
+  uint32_t grp_start[3];  // first entry of each predictor's run in `order`
+};
+
+struct alignas(16) DField {
+  const uint8_t *in;
+  uint64_t in_len;
+  float *out;
+  uint64_t n;             // expected field size
+  uint32_t nblocks_max;
+  uint32_t pad;
+  DState *st;
+  uint32_t *boff;         // payload word offset of every block
+  uint32_t *order;        // block ids grouped by predictor
+  uint32_t *lut;          // 3 x 4096 first-level decode entries
+  uint32_t *slow;         // 3 x (32 first + 32 base + 64 limit words)
+  uint16_t *syms;         // 3 x 65536 canonical symbols
+};
+constexpr int kSlowWords = 128;
+
+// decode-table entry: sym | len << 16; flags
+constexpr uint32_t kLutLong = 1u << 22;
+constexpr uint32_t kLutInvalid = 1u << 23;
+
+// ------------------------------------------------------------ primitives
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+__device__ inline uint32_t float_key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __uint_as_float(u);
+}
+
+template <typename T>
+__device__ inline T wave_incl_scan(T v) {
+  const uint32_t l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (l >= (uint32_t)d) v += o;
+  }
+  return v;
+}
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+
+// field of global block g (fblock0 holds nf+1 prefix entries)
+__device__ inline int find_field(const uint64_t *fblock0, int nf, uint64_t g) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (fblock0[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline uint64_t ld_acquire_u64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release_u64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 2 ulp of a float32 magnitude, exact, as a double
+__device__ inline double guard_of(float am) {
+  uint32_t e = (__float_as_uint(am) >> 23) & 0xffu;
+  int ex = e == 0 ? -149 : (int)e - 150;
+  return 2.0 * ldexp(1.0, ex);
+}
+
+}  // namespace sznb

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of the HIP library ``csrc/libsznb.so``.
+
+Argument marshalling only: device buffers are torch tensors (plumbing for
+HBM allocations and the current HIP stream); every step of compression and
+decompression runs in the library's kernels.  The library must have been
+built (``python -m paper_1711_03888_amd.build``); a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "csrc", "libsznb.so")
+
+OK, EINVAL, ENONFINITE, EEBTOOSMALL, ENOSPC, ECORRUPT, EDEVICE = 0, -1, -2, -3, -4, -5, -6
+PRED_LV, PRED_LCF, PRED_BESTFIT, PRED_LEARNED = 0, 1, 2, 3
+EB_REL = 1 << 4
+HEADER_BYTES = 128
+
+
+def BLOCK_LOG2(b: int) -> int:
+    return (b & 15) << 8
+
+
+class SznbError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        super().__init__("sznb error %d (%s)%s" % (code, strerror(code) if _lib else "", (": " + what) if what else ""))
+        self.code = code
+
+
+_lib = None
+_u64 = ctypes.c_uint64
+_vp = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built; run python -m paper_1711_03888_amd.build" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.sznb_compress_bound.argtypes = [_u64, ctypes.c_uint32]
+        L.sznb_compress_bound.restype = _u64
+        L.sznb_compress_min_capacity.argtypes = [_u64, ctypes.c_uint32]
+        L.sznb_compress_min_capacity.restype = _u64
+        L.sznb_compress_workspace_bytes.argtypes = [ctypes.c_int, _vp, _vp]
+        L.sznb_compress_workspace_bytes.restype = _u64
+        L.sznb_compress.argtypes = [_vp, _u64, ctypes.c_double, ctypes.c_uint32, _vp, _u64, _vp, _vp, _u64, _vp]
+        L.sznb_compress_batch.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.sznb_stream_info.argtypes = [_vp, _u64, _vp, _vp, _vp, _vp]
+        L.sznb_decompress_workspace_bytes.argtypes = [ctypes.c_int, _vp]
+        L.sznb_decompress_workspace_bytes.restype = _u64
+        L.sznb_decompress.argtypes = [_vp, _u64, _vp, _u64, _vp, _u64, _vp]
+        L.sznb_decompress_batch.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.sznb_read_status.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+        L.sznb_profile.argtypes = [ctypes.c_int]
+        L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
+        L.sznb_strerror.argtypes = [ctypes.c_int]
+        L.sznb_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().sznb_strerror(code).decode()
+
+
+def _check(rc: int, what: str = ""):
+    if rc != OK:
+        raise SznbError(rc, what)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _arr(ctype, values):
+    return (ctype * len(values))(*values)
+
+
+def compress_bound(n: int, mode: int) -> int:
+    return int(lib().sznb_compress_bound(n, mode))
+
+
+def compress_workspace_bytes(ns: Sequence[int], modes: Sequence[int]) -> int:
+    return int(lib().sznb_compress_workspace_bytes(len(ns), _arr(_u64, ns), _arr(ctypes.c_uint32, modes)))
+
+
+def decompress_workspace_bytes(ns: Sequence[int]) -> int:
+    return int(lib().sznb_decompress_workspace_bytes(len(ns), _arr(_u64, ns)))
+
+
+def workspace(nbytes: int, device=None) -> torch.Tensor:
+    """Device workspace (the library clears what it needs on every call)."""
+    return torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def _field(x: torch.Tensor) -> torch.Tensor:
+    if x.dtype != torch.float32 or not x.is_cuda or x.dim() != 1 or not x.is_contiguous():
+        raise ValueError("field must be a contiguous 1D float32 CUDA tensor")
+    return x
+
+
+class Compressed:
+    """Device-resident compressed streams and their lengths (device words)."""
+
+    def __init__(self, bufs, lens, ws):
+        self.bufs = bufs
+        self.lens = lens
+        self.ws = ws
+
+    def sizes(self):
+        return [int(v) for v in self.lens.cpu()]
+
+    def streams(self):
+        return [b[:n] for b, n in zip(self.bufs, self.sizes())]
+
+
+def compress_batch_async(fields: Sequence[torch.Tensor], eb, mode, *, caps=None, ws=None, outs=None,
+                         lens=None, stream=None) -> Compressed:
+    """Enqueue compression of several fields in one launch sequence."""
+    fields = [_field(x) for x in fields]
+    nf = len(fields)
+    ebs = list(eb) if isinstance(eb, (list, tuple)) else [float(eb)] * nf
+    modes = list(mode) if isinstance(mode, (list, tuple)) else [int(mode)] * nf
+    ns = [x.numel() for x in fields]
+    if caps is None:
+        caps = [compress_bound(n, m) for n, m in zip(ns, modes)]
+    if outs is None:
+        outs = [torch.empty(c, dtype=torch.uint8, device=x.device) for c, x in zip(caps, fields)]
+    if lens is None:
+        lens = torch.zeros(nf, dtype=torch.int64, device=fields[0].device)
+    wsb = compress_workspace_bytes(ns, modes)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, fields[0].device)
+    rc = lib().sznb_compress_batch(nf, _arr(_vp, [x.data_ptr() for x in fields]), _arr(_u64, ns),
+                                   _arr(ctypes.c_double, ebs), _arr(ctypes.c_uint32, modes),
+                                   _arr(_vp, [o.data_ptr() for o in outs]), _arr(_u64, caps),
+                                   lens.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "compress")
+    return Compressed(outs, lens, ws)
+
+
+def read_status(ws: torch.Tensor, nf: int, stream=None):
+    st = (ctypes.c_int * nf)()
+    first = lib().sznb_read_status(ws.data_ptr(), nf, st, _stream(stream))
+    return first, list(st)
+
+
+def compress_batch(fields, eb, mode, **kw):
+    c = compress_batch_async(fields, eb, mode, **kw)
+    first, st = read_status(c.ws, len(fields))
+    if first != OK:
+        raise SznbError(first, "device status %s" % st)
+    return c.streams()
+
+
+def compress(x: torch.Tensor, eb: float, mode: int = PRED_LV | EB_REL, **kw) -> torch.Tensor:
+    return compress_batch([x], eb, mode, **kw)[0]
+
+
+def stream_info(header: bytes):
+    n = ctypes.c_uint64(0)
+    m = ctypes.c_uint32(0)
+    e = ctypes.c_double(0)
+    t = ctypes.c_uint64(0)
+    buf = ctypes.create_string_buffer(bytes(header[:HEADER_BYTES]), HEADER_BYTES)
+    _check(lib().sznb_stream_info(buf, HEADER_BYTES, ctypes.byref(n), ctypes.byref(m), ctypes.byref(e),
+                                  ctypes.byref(t)), "stream_info")
+    return {"n": n.value, "mode": m.value, "eb_abs": e.value, "total_bytes": t.value}
+
+
+def decompress_batch_async(streams: Sequence[torch.Tensor], ns: Sequence[int], *, outs=None, ws=None, stream=None):
+    nf = len(streams)
+    for s in streams:
+        if s.dtype != torch.uint8 or not s.is_cuda or not s.is_contiguous():
+            raise ValueError("streams must be contiguous uint8 CUDA tensors")
+    if outs is None:
+        outs = [torch.empty(n, dtype=torch.float32, device=s.device) for n, s in zip(ns, streams)]
+    wsb = decompress_workspace_bytes(ns)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, streams[0].device)
+    rc = lib().sznb_decompress_batch(nf, _arr(_vp, [s.data_ptr() for s in streams]),
+                                     _arr(_u64, [s.numel() for s in streams]),
+                                     _arr(_vp, [o.data_ptr() for o in outs]), _arr(_u64, list(ns)),
+                                     ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "decompress")
+    return outs, ws
+
+
+def decompress_batch(streams, ns=None, **kw):
+    if ns is None:
+        ns = [stream_info(bytes(s[:HEADER_BYTES].cpu().numpy()))["n"] for s in streams]
+    outs, ws = decompress_batch_async(streams, ns, **kw)
+    first, st = read_status(ws, len(streams))
+    if first != OK:
+        raise SznbError(first, "device status %s" % st)
+    return outs
+
+
+def decompress(s: torch.Tensor, n: int | None = None, **kw) -> torch.Tensor:
+    return decompress_batch([s], None if n is None else [n], **kw)[0]
+
+
+def profile(enable: bool) -> None:
+    """Bracket every later kernel launch with HIP events (or stop)."""
+    lib().sznb_profile(1 if enable else 0)
+
+
+def profile_summary(max_kernels: int = 64):
+    """{kernel: (total_ms, launches)} of the launches recorded since profile(True)."""
+    names = ctypes.create_string_buffer(32 * max_kernels)
+    tot = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int * max_kernels)()
+    nk = lib().sznb_profile_summary(max_kernels, names, tot, cnt)
+    if nk < 0:
+        raise SznbError(nk, "profile_summary")
+    out = {}
+    for i in range(min(nk, max_kernels)):
+        nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+        out[nm] = (tot[i], cnt[i])
+    return out

@@ -1,0 +1,188 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+The bar: stream bytes identical to the oracle's (codes, predictor choices,
+Huffman codebooks, bit packing), reconstructed floats bit-identical to the
+oracle's decompression, and |x - x~| <= eb_abs on every element.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1711_03888_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1711_03888_amd import sznb  # noqa: E402
+
+
+def _gpu_roundtrip(x, eb, mode):
+    xt = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    s = sznb.compress(xt, eb, mode)
+    y = sznb.decompress(s, x.size)
+    return bytes(s.cpu().numpy()), y.cpu().numpy()
+
+
+def _check(x, eb, mode, label=""):
+    ref = oracle.compress(x, eb, mode)
+    got, y = _gpu_roundtrip(x, eb, mode)
+    if got != ref:
+        h1, h2 = oracle.header(ref), oracle.header(got) if len(got) >= 128 else {}
+        diff = next((i for i in range(min(len(got), len(ref))) if got[i] != ref[i]), None)
+        raise AssertionError("%s stream mismatch: len %d vs %d, first diff at byte %s\nref %s\ngpu %s"
+                             % (label, len(got), len(ref), diff, h1, h2))
+    yref = oracle.decompress(ref)
+    assert np.array_equal(y.view(np.uint32), yref.view(np.uint32)), label
+    if x.size:
+        eb_abs = oracle.header(ref)["eb_abs"]
+        assert np.abs(x.astype(np.float64) - y.astype(np.float64)).max() <= eb_abs, label
+    return ref
+
+
+POLICIES = [sznb.PRED_LV, sznb.PRED_LCF, sznb.PRED_BESTFIT]
+
+
+@pytest.mark.parametrize("policy", POLICIES)
+@pytest.mark.parametrize("eb_rel", [1e-3, 1e-4])
+def test_walk_ragged(policy, eb_rel):
+    print("walk ragged policy=%d eb=%g" % (policy, eb_rel), flush=True)
+    x = datagen.random_walk(3 * 4096 + 777, seed=11)
+    _check(x, eb_rel, policy | sznb.EB_REL, "walk")
+
+
+@pytest.mark.parametrize("policy", POLICIES)
+def test_cosmology_fields(policy):
+    snap = datagen.cosmology(1 << 16, seed=5)
+    for name, x in snap.items():
+        print("cosmo %s policy=%d" % (name, policy), flush=True)
+        _check(x, 1e-4, policy | sznb.EB_REL, name)
+
+
+def test_md_lattice_bestfit_mixes_predictors():
+    md = datagen.md_lattice(cells=(8, 8, 32), seed=3)
+    for name, x in md.items():
+        print("md %s" % name, flush=True)
+        ref = _check(x, 1e-3, sznb.PRED_BESTFIT | sznb.EB_REL, name)
+        h = oracle.header(ref)
+        if name == "zz":
+            pred = np.frombuffer(ref, np.uint8, count=h["nblocks"], offset=h["off_pred"])
+            assert (pred == 1).any()
+
+
+@pytest.mark.parametrize("log2s", [10, 11, 13, 14])
+@pytest.mark.parametrize("policy", [sznb.PRED_LV, sznb.PRED_BESTFIT])
+def test_block_sizes(log2s, policy):
+    print("block 2^%d policy=%d" % (log2s, policy), flush=True)
+    x = datagen.random_walk(5 * (1 << log2s) + 123, seed=log2s)
+    _check(x, 1e-4, policy | sznb.EB_REL | sznb.BLOCK_LOG2(log2s), "S=2^%d" % log2s)
+
+
+@pytest.mark.parametrize("n", [1, 5, 1000, 4096, 4097])
+def test_small_sizes(n):
+    print("small n=%d" % n, flush=True)
+    x = np.random.default_rng(n).normal(0, 1, n).astype(np.float32)
+    _check(x, 1e-3, sznb.PRED_BESTFIT | sznb.EB_REL, "n=%d" % n)
+
+
+def test_empty_and_constant():
+    print("empty/const", flush=True)
+    ref = oracle.compress(np.zeros(0, np.float32), 1e-4, sznb.EB_REL)
+    xt = torch.zeros(0, dtype=torch.float32, device="cuda")
+    s = sznb.compress(xt, 1e-4, sznb.EB_REL)
+    assert bytes(s.cpu().numpy()) == ref
+    assert sznb.decompress(s, 0).numel() == 0
+    x = np.full(5000, -2.5, np.float32)
+    _check(x, 1e-4, sznb.PRED_BESTFIT | sznb.EB_REL, "const")
+    _check(x, 0.1, sznb.PRED_LV, "const-abs")
+
+
+def test_escapes_and_absolute_bound():
+    print("escapes", flush=True)
+    rng = np.random.default_rng(9)
+    x = np.cumsum(rng.normal(0, 1, 20000)).astype(np.float32)
+    x[5000] += 3e4
+    x[12345] -= 5e4
+    for policy in POLICIES:
+        # absolute bound well above 2 ulp of the largest magnitude (~5e4)
+        ref = _check(x, 0.05, policy, "escapes abs")
+        h = oracle.header(ref)
+        nesc = np.frombuffer(ref, np.uint16, count=h["nblocks"], offset=h["off_nesc"])
+        assert nesc.sum() > 0
+
+
+def test_negative_zero_and_negative_values():
+    print("signs", flush=True)
+    x = np.array([-0.0, 0.0, -1.5, 2.25, -0.0] * 2000, np.float32)
+    _check(x, 1e-3, sznb.PRED_BESTFIT | sznb.EB_REL, "signs")
+
+
+def test_device_errors():
+    print("device errors", flush=True)
+    x = np.linspace(0, 1, 9000).astype(np.float32)
+    x[77] = np.nan
+    with pytest.raises(sznb.SznbError) as e:
+        sznb.compress(torch.from_numpy(x).cuda(), 1e-3, sznb.EB_REL)
+    assert e.value.code == sznb.ENONFINITE
+    y = np.linspace(1000, 1008, 9000).astype(np.float32)
+    with pytest.raises(sznb.SznbError) as e:
+        sznb.compress(torch.from_numpy(y).cuda(), 1e-7, sznb.EB_REL)
+    assert e.value.code == sznb.EEBTOOSMALL
+    with pytest.raises(sznb.SznbError) as e:
+        sznb.compress(torch.from_numpy(y).cuda(), -1.0, sznb.EB_REL)
+    assert e.value.code == sznb.EINVAL
+
+
+def test_corrupt_streams_rejected():
+    print("corrupt", flush=True)
+    x = datagen.random_walk(50000, seed=2)
+    s = oracle.compress(x, 1e-4, sznb.PRED_BESTFIT | sznb.EB_REL)
+    good = torch.from_numpy(np.frombuffer(s, np.uint8).copy()).cuda()
+    y = sznb.decompress(good, x.size).cpu().numpy()
+    assert np.array_equal(y, oracle.decompress(s))
+    bad = good.clone()
+    bad[0] ^= 0xFF
+    with pytest.raises(sznb.SznbError) as e:
+        sznb.decompress(bad, x.size)
+    assert e.value.code == sznb.ECORRUPT
+    with pytest.raises(sznb.SznbError):
+        sznb.decompress(good[: good.numel() - 8].clone(), x.size)
+    bad = good.clone()
+    h = oracle.header(s)
+    bad[h["off_cwords"]] = 0xFF
+    bad[h["off_cwords"] + 1] = 0xFF
+    with pytest.raises(sznb.SznbError):
+        sznb.decompress(bad, x.size)
+
+
+def test_batch_equals_single():
+    print("batch", flush=True)
+    xs = [datagen.random_walk(70000, seed=1), datagen.cosmology(1 << 15, seed=4)["vx"],
+          datagen.random_walk(4096, seed=3), np.full(3000, 1.0, np.float32)]
+    modes = [sznb.PRED_LV | sznb.EB_REL, sznb.PRED_BESTFIT | sznb.EB_REL, sznb.PRED_LCF, sznb.PRED_BESTFIT]
+    ebs = [1e-4, 1e-3, 0.01, 1e-3]
+    ts = [torch.from_numpy(x).cuda() for x in xs]
+    streams = sznb.compress_batch(ts, ebs, modes)
+    for x, e, m, s in zip(xs, ebs, modes, streams):
+        assert bytes(s.cpu().numpy()) == oracle.compress(x, e, m)
+    outs = sznb.decompress_batch(streams, [x.size for x in xs])
+    for x, e, m, y in zip(xs, ebs, modes, outs):
+        assert np.array_equal(y.cpu().numpy(), oracle.decompress(oracle.compress(x, e, m)))
+
+
+def test_workspace_reuse_two_calls():
+    print("reuse", flush=True)
+    x1 = datagen.random_walk(100000, seed=7)
+    x2 = datagen.random_walk(30000, seed=8)
+    ws = sznb.workspace(sznb.compress_workspace_bytes([x1.size], [sznb.PRED_BESTFIT | sznb.EB_REL]))
+    for x in (x1, x2, x1):
+        s = sznb.compress(torch.from_numpy(x).cuda(), 1e-4, sznb.PRED_BESTFIT | sznb.EB_REL, ws=ws)
+        assert bytes(s.cpu().numpy()) == oracle.compress(x, 1e-4, sznb.PRED_BESTFIT | sznb.EB_REL)
+
+
+def test_config1_full_bitexact():
+    print("config1 full", flush=True)
+    x = datagen.random_walk()
+    _check(x, 1e-4, sznb.PRED_LV | sznb.EB_REL, "config1")
