@@ -16,13 +16,14 @@ template <int E> __global__ void k_quant(const CField *, int, const uint64_t *, 
 __global__ void k_huff(const CField *, int, uint8_t *, uint64_t);
 __global__ void k_books(const CField *);
 template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, uint64_t, GCtl *);
+__global__ void k_final(const CField *, int);
 uint64_t hscratch_bytes_host();
 
 __global__ void d_prep(const DField *);
 __global__ void d_tables(const DField *);
-__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int);
-__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t);
+__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t *);
 
 constexpr uint64_t kStateStride = 256;
 
@@ -222,6 +223,7 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv) {
   SZNB_LAUNCH("k_huff", k_huff, dim3(P.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host());
   SZNB_LAUNCH("k_books", k_books, dim3(P.nf), dim3(kThreads), 0, s, F);
   if (tb) launch_E(false, P, s, gper);
+  SZNB_LAUNCH("k_final", k_final, dim3((P.nf + 63) / 64), dim3(64), 0, s, F, P.nf);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
@@ -374,10 +376,11 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
                             (int)lds) != hipSuccess)
       return SZNB_EDEVICE;
   }
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, nf, dw, tbase);
+  uint32_t *ticket = &reinterpret_cast<GCtl *>(ws + L.gctl)->ticket;
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, nf, dw, tbase, ticket);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, nf);
-  const int grid = dv->cus * 4;
-  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax);
+  const int grid = dv->cus * 8;
+  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax, ticket);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 

@@ -827,43 +827,61 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
     const uint32_t cwn = (tbits + 31) / 32;
     const uint64_t words = (uint64_t)cwn + tesc;
 
-    // decoupled look-back over the field's earlier blocks
-    if (t == 0) {
+    // decoupled look-back over the field's earlier blocks, 64 at a time by
+    // wave 0: sum the aggregates back to the nearest published prefix
+    if (w == 0) {
+      const uint32_t lane = lane_id();
       uint64_t P = 0;
       if (b == 0) {
-        st_release_u64(&c.lbflag[b], kFlagPre | words);
+        if (lane == 0) st_relaxed_u64(&c.lbflag[0], kFlagPre | words);
       } else {
-        st_release_u64(&c.lbflag[b], kFlagAgg | words);
-        int64_t j = (int64_t)b - 1;
+        if (lane == 0) st_relaxed_u64(&c.lbflag[b], kFlagAgg | words);
+        int64_t base = (int64_t)b - 1;
         for (;;) {
-          uint64_t v = ld_acquire_u64(&c.lbflag[j]);
-          if (v == 0) { __builtin_amdgcn_s_sleep(1); continue; }
-          P += v & kValMask;
-          if ((v >> 62) == 2) break;
-          j--;
+          const int64_t j = base - (int64_t)lane;
+          const uint64_t v = j >= 0 ? ld_relaxed_u64(&c.lbflag[j]) : kFlagPre;
+          const uint64_t pre = __ballot((v >> 62) == 2);
+          const uint64_t zero = __ballot(v == 0);
+          if (pre) {
+            const uint32_t pl = (uint32_t)__builtin_ctzll(pre);
+            const uint64_t upto = pl == 63 ? ~0ull : ((2ull << pl) - 1);
+            if (zero & upto) { __builtin_amdgcn_s_sleep(1); continue; }
+            P += wave_sum((unsigned long long)(lane <= pl ? (v & kValMask) : 0ull));
+            break;
+          }
+          if (zero) { __builtin_amdgcn_s_sleep(1); continue; }
+          P += wave_sum((unsigned long long)(v & kValMask));
+          base -= kWave;
         }
-        st_release_u64(&c.lbflag[b], kFlagPre | (P + words));
+        if (lane == 0) st_relaxed_u64(&c.lbflag[b], kFlagPre | (P + words));
       }
-      s_prefix = P;
+      if (lane == 0) s_prefix = P;
     }
     for (uint32_t i = t; i < cwn; i += kThreads) s_words[i] = 0u;
     __syncthreads();
-    // MSB-first packing of this thread's codewords
-    uint32_t o = bit0;
+    // MSB-first packing: whole words of this thread's run are stored, the
+    // first and last word (possibly shared with a neighbour) are OR-ed in
+    {
+      uint32_t wi = bit0 >> 5;
+      const uint32_t wfirst = wi;
+      uint32_t na = bit0 & 31u;
+      uint64_t acc = 0;
 #pragma unroll
-    for (int e = 0; e < E; e++) {
-      const uint32_t l = cw[e] >> 24, code = cw[e] & 0xffffffu;
-      if (l) {
-        const uint32_t wi = o >> 5, sh = o & 31u;
-        if (sh + l <= 32u) {
-          atomicOr(&s_words[wi], code << (32u - sh - l));
-        } else {
-          const uint32_t over = sh + l - 32u;
-          atomicOr(&s_words[wi], code >> over);
-          atomicOr(&s_words[wi + 1], code << (32u - over));
+      for (int e = 0; e < E; e++) {
+        const uint32_t l = cw[e] >> 24;
+        if (l) {
+          acc |= (uint64_t)(cw[e] & 0xffffffu) << (64u - na - l);
+          na += l;
+          if (na >= 32u) {
+            const uint32_t word = (uint32_t)(acc >> 32);
+            if (wi == wfirst) atomicOr(&s_words[wi], word); else s_words[wi] = word;
+            wi++;
+            acc <<= 32;
+            na -= 32u;
+          }
         }
-        o += l;
       }
+      if (bits && na) atomicOr(&s_words[wi], (uint32_t)(acc >> 32));
     }
     __syncthreads();
     const uint64_t P = s_prefix;
@@ -887,24 +905,29 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
       reinterpret_cast<uint16_t *>(c.out + c.sec.cwords)[b] = (uint16_t)cwn;
       reinterpret_cast<uint16_t *>(c.out + c.sec.nesc)[b] = (uint16_t)tesc;
       if (b + 1 == c.nblocks) st->payload_words = P + words;
-      __threadfence();
-      const uint32_t done = atomicAdd(&st->blocks_done, 1u);
-      if (done + 1 == c.nblocks) {
-        __threadfence();
-        const uint64_t pw = __hip_atomic_load(&st->payload_words, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t tb = st->off_payload + 4 * pw;
-        const int status = __hip_atomic_load(&st->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        if (status != 0 || tb > c.out_cap) {
-          st->status = SZNB_ENOSPC;
-          if (c.out_len) *c.out_len = 0;
-        } else {
-          put64(c.out, H_PWORDS, pw);
-          put64(c.out, H_TOTAL, tb);
-          if (c.out_len) *c.out_len = tb;
-        }
-      }
     }
     __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------- final
+
+// After the pack kernel: payload size, total size and output length.
+__global__ void k_final(const CField *__restrict__ F, int nf) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const CField &c = F[f];
+  FState *st = c.st;
+  if (st->is_const || (st->status != 0 && st->status != SZNB_ENOSPC)) return;
+  const uint64_t pw = st->payload_words;
+  const uint64_t tb = st->off_payload + 4 * pw;
+  if (st->status != 0 || tb > c.out_cap) {
+    st->status = SZNB_ENOSPC;
+    if (c.out_len) *c.out_len = 0;
+  } else {
+    put64(c.out, H_PWORDS, pw);
+    put64(c.out, H_TOTAL, tb);
+    if (c.out_len) *c.out_len = tb;
   }
 }
 

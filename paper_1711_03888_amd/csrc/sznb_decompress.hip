@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
     for (uint32_t l = 1; l <= ml; l++) len += s_limit[l] <= win;
     uint32_t ent;
     if (len > ml) ent = kLutInvalid | 0xffffu | (1u << 16);
-    else if (len > (uint32_t)kLutBits) ent = kLutLong;
+    else if (len > (uint32_t)kLutBits) ent = kLutLong | (len << 16);  // shortest code under this prefix
     else {
       const uint32_t code = (uint32_t)(win >> (32 - len));
       ent = (uint32_t)syms[s_base[len] + (code - s_first[len])] | (len << 16);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
 // tbase[p] for p = 3 f + k: first decode task of (stream f, predictor k); a
 // task is up to `dw` consecutive blocks of one group.
 __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t dw,
-                                                    uint32_t *tbase) {
+                                                    uint32_t *tbase, uint32_t *ticket) {
   __shared__ uint32_t s_tot[kThreads / kWave];
   const int t = threadIdx.x, w = t / kWave;
   const int np = 3 * nf;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D
       if (st->status == 0 && !st->is_const) run += (st->grp_count[p % 3] + dw - 1) / dw;
     }
   }
-  if (t == kThreads - 1) tbase[np] = run;
+  if (t == kThreads - 1) { tbase[np] = run; *ticket = 0; }
 }
 
 __global__ void d_const(const DField *__restrict__ D, int nf) {
@@ -266,12 +266,33 @@ struct DecTab {
   uint32_t maxlen;
 };
 
-// next 32 bits of the block's code region at bit `pos` (zeros past the end)
-__device__ inline uint32_t window_at(const uint32_t *wp, uint32_t cw, uint32_t pos) {
-  const uint32_t wi = pos >> 5, sh = pos & 31u;
-  const uint32_t w0 = wi < cw ? wp[wi] : 0u;
-  const uint32_t w1 = wi + 1 < cw ? wp[wi + 1] : 0u;
-  return sh ? (w0 << sh) | (w1 >> (32u - sh)) : w0;
+// Per-lane reader of the block's code region: a 64-bit window holding at
+// least 32 unread bits and one prefetched word (zeros past the end).
+struct BitReader {
+  const uint32_t *wp;
+  uint32_t cw, wi, pend, nb;
+  uint64_t buf;
+};
+__device__ inline void br_init(BitReader &r, const uint32_t *wp, uint32_t cw, uint32_t pos) {
+  r.wp = wp;
+  r.cw = cw;
+  const uint32_t w = pos >> 5, sh = pos & 31u;
+  const uint32_t w0 = w < cw ? wp[w] : 0u, w1 = w + 1 < cw ? wp[w + 1] : 0u;
+  r.buf = (((uint64_t)w0 << 32) | w1) << sh;
+  r.nb = 64u - sh;
+  r.wi = w + 2;
+  r.pend = r.wi < cw ? wp[r.wi] : 0u;
+}
+__device__ inline uint32_t br_peek(const BitReader &r) { return (uint32_t)(r.buf >> 32); }
+__device__ inline void br_skip(BitReader &r, uint32_t len) {
+  r.buf <<= len;
+  r.nb -= len;
+  if (r.nb < 32u) {
+    r.buf |= (uint64_t)r.pend << (32u - r.nb);
+    r.nb += 32u;
+    r.wi++;
+    r.pend = r.wi < r.cw ? r.wp[r.wi] : 0u;
+  }
 }
 
 // decode one codeword from a 32-bit window: returns sym | len << 16, or an
@@ -279,7 +300,7 @@ __device__ inline uint32_t window_at(const uint32_t *wp, uint32_t cw, uint32_t p
 __device__ inline uint32_t decode_one(const DecTab &T, uint32_t win) {
   uint32_t e = T.lut[win >> (32 - kLutBits)];
   if (e & kLutLong) {
-    uint32_t len = kLutBits + 1;
+    uint32_t len = (e >> 16) & 31u;
     while (len <= T.maxlen) {
       const uint64_t lim = (uint64_t)T.limit[2 * len] | ((uint64_t)T.limit[2 * len + 1] << 32);
       if ((uint64_t)win < lim) break;
@@ -313,11 +334,17 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
   __builtin_amdgcn_wave_barrier();
   // phase 1: speculative decode of the own range
   uint32_t pos = s, cnt = 0;
-  while (pos < e) {
-    const uint32_t r = decode_one(T, window_at(wp, cw, pos));
-    atomicOr(&bm[pos >> 5], 1u << (pos & 31u));
-    pos += (r >> 16) & 31u;
-    cnt++;
+  if (s < e) {
+    BitReader br;
+    br_init(br, wp, cw, s);
+    while (pos < e) {
+      const uint32_t r = decode_one(T, br_peek(br));
+      const uint32_t ln = (r >> 16) & 31u;
+      atomicOr(&bm[pos >> 5], 1u << (pos & 31u));
+      pos += ln;
+      br_skip(br, ln);
+      cnt++;
+    }
   }
   // exit1: where the first-pass path leaves the range (the true exit once a
   // corrected path lands on a first-pass mark)
@@ -332,11 +359,16 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
     if (changed) {
       uint32_t p = tin, c2 = 0;
       bool synced = false;
-      while (p < e) {
-        if ((bm[p >> 5] >> (p & 31u)) & 1u) { synced = true; break; }
-        const uint32_t r = decode_one(T, window_at(wp, cw, p));
-        p += (r >> 16) & 31u;
-        c2++;
+      if (p < e) {
+        BitReader br;
+        br_init(br, wp, cw, p);
+        while (p < e) {
+          if ((bm[p >> 5] >> (p & 31u)) & 1u) { synced = true; break; }
+          const uint32_t ln = (decode_one(T, br_peek(br)) >> 16) & 31u;
+          p += ln;
+          br_skip(br, ln);
+          c2++;
+        }
       }
       if (synced) {
         uint32_t pc = __popc(bm[p >> 5] & (~0u << (p & 31u)));
@@ -360,12 +392,18 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
   uint32_t invalid = 0;
   {
     uint32_t p = start, i = o;
-    while (p < e && i < len) {
-      const uint32_t r = decode_one(T, window_at(wp, cw, p));
-      if (r & kLutInvalid) invalid = 1;
-      q16[qidx(i)] = (uint16_t)(r & 0xffffu);
-      p += (r >> 16) & 31u;
-      i++;
+    if (p < e && i < len) {
+      BitReader br;
+      br_init(br, wp, cw, p);
+      while (p < e && i < len) {
+        const uint32_t r = decode_one(T, br_peek(br));
+        const uint32_t ln = (r >> 16) & 31u;
+        if (r & kLutInvalid) invalid = 1;
+        q16[qidx(i)] = (uint16_t)(r & 0xffffu);
+        p += ln;
+        br_skip(br, ln);
+        i++;
+      }
     }
   }
   __builtin_amdgcn_wave_barrier();
@@ -445,20 +483,23 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
 
 // dw waves per workgroup; dynamic LDS: lut | slow | dw regions of 4*Smax bytes
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
-                         uint32_t dw, uint32_t smax) {
+                         uint32_t dw, uint32_t smax, uint32_t *ticket) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
   uint32_t *s_slow = s_lut + (1u << kLutBits);
   uint8_t *regs = reinterpret_cast<uint8_t *>(s_slow + kSlowWords);
-  __shared__ int s_bad;
+  __shared__ uint32_t s_task;
   const int t = threadIdx.x;
   const uint32_t w = t / kWave;
   const int np = 3 * nf;
   const uint32_t T = tbase[np];
-  const uint32_t G = gridDim.x;
-  const uint32_t t0 = (uint32_t)(((uint64_t)T * blockIdx.x) / G), t1 = (uint32_t)(((uint64_t)T * (blockIdx.x + 1)) / G);
   int cur = -1;
-  for (uint32_t task = t0; task < t1; task++) {
+  for (;;) {
+    if (t == 0) s_task = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const uint32_t task = s_task;
+    __syncthreads();
+    if (task >= T) break;
     // pair of this task
     int lo = 0, hi = np - 1;
     while (lo < hi) {
@@ -474,7 +515,6 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
       for (uint32_t i = t; i < (1u << kLutBits); i += blockDim.x) s_lut[i] = gl[i];
       const uint32_t *gs = df.slow + (uint64_t)k * kSlowWords;
       for (uint32_t i = t; i < (uint32_t)kSlowWords; i += blockDim.x) s_slow[i] = gs[i];
-      if (t == 0) s_bad = 0;
       __syncthreads();
       cur = pair;
     }

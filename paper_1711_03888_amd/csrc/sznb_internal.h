@@ -181,11 +181,14 @@ __device__ inline int find_field(const uint64_t *fblock0, int nf, uint64_t g) {
   return lo;
 }
 
-__device__ inline uint64_t ld_acquire_u64(const uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Coherent (agent-scope) relaxed accesses.  Acquire/release would add cache
+// write-back and invalidation to every access; the look-back words carry all
+// the information their readers need, so none is required.
+__device__ inline uint64_t ld_relaxed_u64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_release_u64(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_relaxed_u64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // 2 ulp of a float32 magnitude, exact, as a double
