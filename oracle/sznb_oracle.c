@@ -335,6 +335,34 @@ static void put_bits(bw_t *b, uint32_t code, int len)
     }
 }
 
+/* ----------------------------------------------------------- skip table */
+
+/* reading: a block's code bits are cut into R word-aligned ranges, range l
+ * starting at bit 32 floor(l cw / R) (cw = code words of the block,
+ * R = min(64, max(1, floor(cw / 8)))).  For every range after the first the
+ * stream stores the distance from the range start to the first codeword that
+ * starts at or after it, in w = bitlen(maxlen - 1) bits, MSB first, in words
+ * placed ahead of the code words.  A decoder can then begin a codeword in
+ * every range without decoding the ones before it. */
+static uint32_t n_ranges(uint64_t cw)
+{
+    uint64_t r = cw / 8;
+    if (r < 1) r = 1;
+    if (r > 64) r = 64;
+    return (uint32_t)r;
+}
+static uint32_t skip_width(int maxlen)
+{
+    uint32_t w = 0;
+    while ((1 << w) < maxlen) w++;
+    return w;
+}
+static uint64_t skip_words(uint64_t cw, int maxlen)
+{
+    return ((uint64_t)(n_ranges(cw) - 1) * skip_width(maxlen) + 31) / 32;
+}
+static uint64_t range_start(uint32_t l, uint64_t cw) { return 32 * ((l * cw) / n_ranges(cw)); }
+
 /* -------------------------------------------------------------- stream */
 
 /* Stream layout (all little-endian), header of 128 bytes:
@@ -347,9 +375,9 @@ static void put_bits(bw_t *b, uint32_t code, int len)
  * only), pfirst i32[nb], cwords u16[nb], nesc u16[nb]; books: for each
  * predictor k with n_sym[k] > 0, blcount u32[max_len[k]] then syms
  * u16[n_sym[k]] in canonical order, padded to 8 bytes; payload u32[].  Each
- * block's payload is its code bits (MSB first, coded with the codebook of the
- * block's predictor), zero-padded to a 32-bit word, then its escaped residuals
- * as i32 words in element order.
+ * block's payload is its skip table (see above), its code bits (MSB first,
+ * coded with the codebook of the block's predictor) zero-padded to a 32-bit
+ * word, then its escaped residuals as i32 words in element order.
  * reading: one Huffman codebook per predictor -- a block is entropy coded with
  * the code built from the residuals of all blocks that chose the same
  * predictor, so blocks with different residual laws do not share a code. */
@@ -468,7 +496,7 @@ int sznbref_compress_blocks(const float *x, uint64_t n, double eb, uint32_t mode
         }
         cwords[b] = (uint16_t)((bits + 31) / 32);
         nesc[b] = (uint16_t)ne;
-        payload_words += cwords[b] + ne;
+        payload_words += skip_words(cwords[b], maxlen[pred[b]]) + cwords[b] + ne;
     }
 
     uint64_t off_pred = 0, o = HDR;
@@ -526,10 +554,31 @@ int sznbref_compress_blocks(const float *x, uint64_t n, double eb, uint32_t mode
         bw_t bw;
         bw.w = calloc((uint64_t)cwords[b] + 1, sizeof(uint32_t));
         bw.nbits = 0;
-        for (uint64_t j = 0; j < blen; j++) put_bits(&bw, ck[code[b * S + j]], lk[code[b * S + j]]);
+        uint64_t *cstart = malloc(sizeof(uint64_t) * (blen + 1));
+        for (uint64_t j = 0; j < blen; j++) {
+            cstart[j] = bw.nbits;
+            put_bits(&bw, ck[code[b * S + j]], lk[code[b * S + j]]);
+        }
+        /* skip table: first codeword start at or after each range start */
+        const uint64_t cwn = cwords[b];
+        const uint32_t R = n_ranges(cwn), wdt = skip_width(maxlen[pred[b]]);
+        const uint64_t skw = skip_words(cwn, maxlen[pred[b]]);
+        bw_t sk;
+        sk.w = calloc(skw + 1, sizeof(uint32_t));
+        sk.nbits = 0;
+        uint64_t j = 0;
+        for (uint32_t l = 1; l < R; l++) {
+            uint64_t st = range_start(l, cwn);
+            while (j < blen && cstart[j] < st) j++;
+            put_bits(&sk, (uint32_t)(cstart[j] - st), (int)wdt);
+        }
+        for (uint64_t k = 0; k < skw; k++) put_u32(s, off_payload + 4 * (wpos + k), sk.w[k]);
+        wpos += skw;
         for (uint64_t k = 0; k < cwords[b]; k++) put_u32(s, off_payload + 4 * (wpos + k), bw.w[k]);
         wpos += cwords[b];
         free(bw.w);
+        free(sk.w);
+        free(cstart);
         for (uint64_t j = 0; j < blen; j++)
             if (code[b * S + j] == 0) { put_u32(s, off_payload + 4 * wpos, (uint32_t)res[b * S + j]); wpos++; }
     }
@@ -613,11 +662,25 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
         int32_t p0 = (int32_t)get_u32(s, off_pfirst + 4 * b);
         uint64_t cwn = get_u16(s, off_cwords + 2 * b);
         uint64_t ne = get_u16(s, off_nesc + 2 * b);
-        if (k > 2 || bk[k].maxlen == 0 || wpos + cwn + ne > pw) { free(y); free(r); return E_CORRUPT; }
+        if (k > 2 || bk[k].maxlen == 0) { free(y); free(r); return E_CORRUPT; }
         const book_t *B = &bk[k];
-        uint64_t base = off_payload + 4 * wpos;
+        const uint64_t skw = skip_words(cwn, B->maxlen);
+        if (wpos + skw + cwn + ne > pw) { free(y); free(r); return E_CORRUPT; }
+        const uint64_t sbase = off_payload + 4 * wpos;
+        uint64_t base = sbase + 4 * skw;
         uint64_t bit = 0, esc = 0;
+        const uint32_t R = n_ranges(cwn), wdt = skip_width(B->maxlen);
+        uint32_t rnext = 1;  /* next range whose skip is checked */
+        uint64_t sbit = 0;
         for (uint64_t j = 0; j < blen; j++) {
+            /* every range start passed on the way to this codeword must point at it */
+            while (rnext < R && range_start(rnext, cwn) <= bit) {
+                uint32_t v = 0;
+                for (uint32_t t = 0; t < wdt; t++, sbit++)
+                    v = (v << 1) | ((get_u32(s, sbase + 4 * (sbit >> 5)) >> (31 - (sbit & 31))) & 1u);
+                if (range_start(rnext, cwn) + v != bit) { free(y); free(r); return E_CORRUPT; }
+                rnext++;
+            }
             /* canonical decode, one bit at a time */
             uint32_t v = 0;
             int l = 0, found = 0;
@@ -643,7 +706,7 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
                 r[j] = (int32_t)sym - RADIUS;
             }
         }
-        if (esc != ne || r[0] != 0) { free(y); free(r); return E_CORRUPT; }
+        if (esc != ne || r[0] != 0 || rnext != R) { free(y); free(r); return E_CORRUPT; }
         /* invert the prediction: d_j = q_j - q_0 from residuals, values before
          * the block equal to the anchor */
         int64_t d1 = 0, d2 = 0, d3 = 0;
@@ -657,7 +720,7 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
             y[b * S + j] = (float)fma((double)pi, step, (double)mn);
             d3 = d2; d2 = d1; d1 = d0;
         }
-        wpos += cwn + ne;
+        wpos += skw + cwn + ne;
     }
     free(r);
     *out = y;

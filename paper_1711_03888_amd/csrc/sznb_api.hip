@@ -23,7 +23,7 @@ __global__ void d_prep(const DField *);
 __global__ void d_tables(const DField *);
 __global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int);
-__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t *);
+__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *);
 
 constexpr uint64_t kStateStride = 256;
 
@@ -56,11 +56,11 @@ struct ProfScope {
     hipEvent_t a = prof_event();
     b = prof_event();
     if (!a || !b) { b = nullptr; return; }
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     g_prof.push_back({name, a, b});
   }
   ~ProfScope() {
-    if (b) hipEventRecord(b, s);
+    if (b) (void)hipEventRecord(b, s);
   }
 };
 #define SZNB_LAUNCH(name, kernel, grid, block, lds, stream, ...)        \
@@ -336,11 +336,16 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
       return SZNB_EDEVICE;
   }
   if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
-  uint32_t smax = 1024;
+  uint32_t smax = 1024, nsym_max = 0;
   for (int f = 0; f < nf; f++) {
     uint32_t S;
     std::memcpy(&S, hdr.data() + 128ull * f + H_S, 4);
     if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
+    for (int k = 0; k < 3; k++) {
+      uint32_t ns;
+      std::memcpy(&ns, hdr.data() + 128ull * f + H_NSYM + 4 * k, 4);
+      if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
+    }
   }
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   std::vector<DField> hf(nf);
@@ -366,11 +371,22 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
   uint32_t *tbase = reinterpret_cast<uint32_t *>(ws + L.tbase);
   SZNB_LAUNCH("d_prep", d_prep, dim3(nf), dim3(kThreads), 0, stream, D);
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * nf), dim3(kThreads), 0, stream, D);
-  // waves per workgroup: regions of 4*smax bytes next to the tables
-  uint32_t dw = 8192u / smax;
-  if (dw < 1) dw = 1;
-  if (dw > 4) dw = 4;
-  const size_t lds = 4ull * (1u << kLutBits) + 4ull * kSlowWords + 4ull * smax * dw;
+  // waves per workgroup and symbol table placement: most resident waves per
+  // CU under the LDS of a CU (tables once per workgroup, one region per wave)
+  const size_t lds_cu = dv->lds_per_block ? dv->lds_per_block : 65536;
+  const size_t tables = 4ull * (1u << kLutBits) + 4ull * 64 + 8ull * 32;
+  uint32_t symcap = nsym_max;
+  const size_t per_wave = 4ull * (smax + 64);
+  if (tables + ((2ull * symcap + 15) & ~15ull) + per_wave > lds_cu) symcap = 0;
+  const size_t symb = (2ull * symcap + 15) & ~15ull;
+  uint32_t dw = 1, best = 0;
+  for (uint32_t cand = 1; cand <= 8; cand++) {
+    const size_t need = tables + symb + cand * per_wave;
+    if (need > lds_cu) break;
+    const uint32_t waves = cand * (uint32_t)(lds_cu / need);
+    if (waves >= best) { best = waves; dw = cand; }
+  }
+  const size_t lds = tables + symb + dw * per_wave;
   if (lds > 65536) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(d_decode), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
@@ -379,8 +395,9 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
   uint32_t *ticket = &reinterpret_cast<GCtl *>(ws + L.gctl)->ticket;
   SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, nf, dw, tbase, ticket);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, nf);
-  const int grid = dv->cus * 8;
-  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax, ticket);
+  const int grid = dv->cus * (int)std::max<size_t>(1, lds_cu / lds);
+  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax, symcap,
+              ticket);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 

@@ -770,7 +770,7 @@ template <int E>
 __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F, int nf,
                                                    const uint64_t *__restrict__ fb0, uint64_t total, GCtl *gc) {
   constexpr int S = E * kThreads;
-  constexpr int CWMAX = S * kLMax / 32;
+  constexpr int CWMAX = S * kLMax / 32 + 16;  // code words plus the skip table
   __shared__ uint32_t s_words[CWMAX];
   __shared__ int32_t s_tail[3 * kThreads];
   __shared__ int32_t s_p0;
@@ -825,7 +825,9 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
     const uint32_t bit0 = (uint32_t)ex, esc0 = (uint32_t)(ex >> 32);
     const uint32_t tbits = (uint32_t)tot, tesc = (uint32_t)(tot >> 32);
     const uint32_t cwn = (tbits + 31) / 32;
-    const uint64_t words = (uint64_t)cwn + tesc;
+    const uint32_t R = n_ranges(cwn), swd = skip_width(st->maxlen[pred]);
+    const uint32_t skw = skip_words(cwn, st->maxlen[pred]);
+    const uint64_t words = (uint64_t)skw + cwn + tesc;
 
     // decoupled look-back over the field's earlier blocks, 64 at a time by
     // wave 0: sum the aggregates back to the nearest published prefix
@@ -857,11 +859,37 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
       }
       if (lane == 0) s_prefix = P;
     }
-    for (uint32_t i = t; i < cwn; i += kThreads) s_words[i] = 0u;
+    for (uint32_t i = t; i < skw + cwn; i += kThreads) s_words[i] = 0u;
     __syncthreads();
+    // skip table entries of the range starts inside this thread's bits
+    if (bits && R > 1) {
+      const uint32_t w0 = (bit0 + 31) >> 5;
+      uint32_t lr = (uint32_t)(((uint64_t)w0 * R + cwn - 1) / cwn);
+      if (lr < 1) lr = 1;
+      for (; lr < R; lr++) {
+        const uint32_t st0 = range_start(lr, cwn, R);
+        if (st0 >= bit0 + bits) break;
+        uint32_t o = bit0, T = bit0 + bits;
+#pragma unroll
+        for (int e = 0; e < E; e++) {
+          if (o >= st0 && T == bit0 + bits) T = o;
+          o += cw[e] >> 24;
+        }
+        const uint32_t v = T - st0, pos = (lr - 1) * swd;
+        const uint32_t wi = pos >> 5, sh = pos & 31u;
+        if (sh + swd <= 32u) {
+          atomicOr(&s_words[wi], v << (32u - sh - swd));
+        } else {
+          const uint32_t over = sh + swd - 32u;
+          atomicOr(&s_words[wi], v >> over);
+          atomicOr(&s_words[wi + 1], v << (32u - over));
+        }
+      }
+    }
     // MSB-first packing: whole words of this thread's run are stored, the
     // first and last word (possibly shared with a neighbour) are OR-ed in
     {
+      uint32_t *s_code = s_words + skw;
       uint32_t wi = bit0 >> 5;
       const uint32_t wfirst = wi;
       uint32_t na = bit0 & 31u;
@@ -874,14 +902,14 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
           na += l;
           if (na >= 32u) {
             const uint32_t word = (uint32_t)(acc >> 32);
-            if (wi == wfirst) atomicOr(&s_words[wi], word); else s_words[wi] = word;
+            if (wi == wfirst) atomicOr(&s_code[wi], word); else s_code[wi] = word;
             wi++;
             acc <<= 32;
             na -= 32u;
           }
         }
       }
-      if (bits && na) atomicOr(&s_words[wi], (uint32_t)(acc >> 32));
+      if (bits && na) atomicOr(&s_code[wi], (uint32_t)(acc >> 32));
     }
     __syncthreads();
     const uint64_t P = s_prefix;
@@ -889,9 +917,9 @@ __global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F,
     const bool fits = (wbase + words) * 4 <= c.out_cap;
     uint32_t *ow = reinterpret_cast<uint32_t *>(c.out);
     if (fits) {
-      for (uint32_t i = t; i < cwn; i += kThreads) ow[wbase + i] = s_words[i];
+      for (uint32_t i = t; i < skw + cwn; i += kThreads) ow[wbase + i] = s_words[i];
       if (nesc) {
-        uint32_t ei = esc0;
+        uint32_t ei = skw + esc0;
 #pragma unroll
         for (int e = 0; e < E; e++) {
           const bool valid = (uint32_t)t * E + e < len;

@@ -5,20 +5,11 @@
 //   d_tables   canonical decode tables per (stream, predictor): a 4096-entry
 //              first-level table and per-length limits for longer codes
 //   d_tasks    task prefix over (stream, predictor) groups
-//   d_decode   one wave per block: self-synchronising parallel Huffman decode
-//              of the block's bits, escapes, inverse prediction by a wave scan
-//              of affine prefix maps, reconstruction x~ = fl32(fma(p, step, mn))
+//   d_decode   one wave per block: parallel Huffman decode of the block's
+//              ranges from the skip-table entry points (one lane per range),
+//              escapes, inverse prediction by a wave scan of affine prefix
+//              maps, reconstruction x~ = fl32(fma(p, step, mn))
 //   d_const    constant streams
-//
-// Self-synchronising decode: the block's code bits are cut into 64 word-
-// aligned ranges, one per lane.  Each lane first decodes from the start of
-// its range as if a codeword began there, marking the positions it decodes
-// in an LDS bitmap.  A lane's true start is where its left neighbour's
-// decoding leaves its range; a lane whose guess was wrong decodes again from
-// the true start until it lands on a marked position -- from there on its
-// first pass was right (prefix codes resynchronise) -- and the symbols it
-// owns are the ones decoded plus the marks counted after that point.  The
-// correction repeats until no start moves (at most 64 rounds, usually one).
 #include "sznb_internal.h"
 
 namespace sznb {
@@ -109,9 +100,9 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D)
     const uint32_t cw = rd16(in, st->off_cwords + 2ull * b), ne = rd16(in, st->off_nesc + 2ull * b);
     const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
     const uint32_t blen = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
-    if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) bad = 1;
-    else cnt[k]++;
-    words += cw + ne;
+    if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) { bad = 1; continue; }
+    cnt[k]++;
+    words += skip_words(cw, st->maxlen[k]) + cw + ne;
   }
   // workgroup exclusive scans of (words, cnt0, cnt1, cnt2)
   uint32_t v[4] = {words, cnt[0], cnt[1], cnt[2]}, ex[4], tot[4];
@@ -139,8 +130,9 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D)
   uint32_t run = ex[0], gpos[3] = {gstart[0] + ex[1], gstart[1] + ex[2], gstart[2] + ex[3]};
   for (uint32_t b = lo; b < hi; b++) {
     df.boff[b] = run;
-    run += rd16(in, st->off_cwords + 2ull * b) + rd16(in, st->off_nesc + 2ull * b);
     const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
+    const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
+    run += skip_words(cw, st->maxlen[k]) + cw + rd16(in, st->off_nesc + 2ull * b);
     df.order[gpos[k]++] = b;
   }
   if (t == 0) {
@@ -258,11 +250,11 @@ __global__ void d_const(const DField *__restrict__ D, int nf) {
 // --------------------------------------------------------------- decode
 
 struct DecTab {
-  const uint32_t *lut;     // LDS
-  const uint32_t *first;   // LDS
-  const uint32_t *base;    // LDS
-  const uint32_t *limit;   // LDS (lo, hi pairs)
-  const uint16_t *syms;    // global
+  const uint32_t *lut;     // LDS: 4096 first-level entries
+  const uint32_t *first;   // LDS: first canonical code of each length
+  const uint32_t *base;    // LDS: canonical index of that code
+  const uint64_t *limit;   // LDS: end of the left-justified code range of each length
+  const uint16_t *syms;    // LDS when it fits, else global
   uint32_t maxlen;
 };
 
@@ -295,111 +287,99 @@ __device__ inline void br_skip(BitReader &r, uint32_t len) {
   }
 }
 
-// decode one codeword from a 32-bit window: returns sym | len << 16, or an
-// invalid marker with length 1
-__device__ inline uint32_t decode_one(const DecTab &T, uint32_t win) {
-  uint32_t e = T.lut[win >> (32 - kLutBits)];
+// length of the codeword at the front of a 32-bit window (1 for a pattern
+// that is no codeword: speculative decoding keeps going)
+__device__ inline uint32_t decode_len(const DecTab &T, uint32_t win) {
+  const uint32_t e = T.lut[win >> (32 - kLutBits)];
+  uint32_t len = (e >> 16) & 31u;
   if (e & kLutLong) {
-    uint32_t len = (e >> 16) & 31u;
-    while (len <= T.maxlen) {
-      const uint64_t lim = (uint64_t)T.limit[2 * len] | ((uint64_t)T.limit[2 * len + 1] << 32);
-      if ((uint64_t)win < lim) break;
-      len++;
-    }
-    if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
-    const uint32_t code = win >> (32 - len);
-    return (uint32_t)T.syms[T.base[len] + (code - T.first[len])] | (len << 16);
+    while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
+    if (len > T.maxlen) len = 1;
   }
-  return e;
+  return len;
+}
+// symbol | length << 16 (plus the invalid flag for a pattern that is no codeword)
+__device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
+  const uint32_t e = T.lut[win >> (32 - kLutBits)];
+  if (!(e & kLutLong)) return e;
+  uint32_t len = (e >> 16) & 31u;
+  while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
+  if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
+  const uint32_t code = win >> (32 - len);
+  return (uint32_t)T.syms[T.base[len] + (code - T.first[len])] | (len << 16);
 }
 
-// one wave decodes block b of a stream into LDS floats and stores them
-__device__ void decode_block(const DField &df, const DState *st, const DecTab &T, uint32_t b, uint8_t *reg,
-                             int *bad_flag) {
+// One wave decodes block b of a stream and stores its floats.
+// Lane l < R decodes the codewords starting in range l of the block's code
+// bits, from the first codeword the skip table points at: one pass counts
+// them, a second writes them after the counts of the lanes before it.
+// Region layout (4 (S + 64) bytes): lane l owns float slots
+// [l (E2+1), l (E2+1) + E2) (E2 = S/64; the one-slot skew keeps the 64 lanes
+// on distinct LDS banks), and the u16 codes of its chunk sit in the upper
+// half of its slot, so writing float i only overwrites codes it has read.
+__device__ __forceinline__ void decode_block(const DField &df, const DState *st, const DecTab &T, uint32_t b,
+                                             uint8_t *reg, uint32_t lg, int *bad_flag) {
   const uint32_t l = lane_id();
   const uint8_t *in = df.in;
   const uint32_t S = st->S;
-  const uint32_t E2 = S / kWave;
+  const uint32_t E2 = 1u << lg;
   const uint32_t len = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
   const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
   const uint32_t ne = rd16(in, st->off_nesc + 2ull * b);
   const uint32_t k = st->policy >= 2 ? in[st->off_pred + b] : st->policy;
   const int32_t p0 = (int32_t)rd32(in, st->off_pfirst + 4ull * b);
-  const uint32_t *wp = reinterpret_cast<const uint32_t *>(in + st->off_payload) + df.boff[b];
-  uint32_t *bm = reinterpret_cast<uint32_t *>(reg);
+  const uint32_t R = n_ranges(cw), swd = skip_width(T.maxlen), skw = skip_words(cw, T.maxlen);
+  const uint32_t *sk = reinterpret_cast<const uint32_t *>(in + st->off_payload) + df.boff[b];
+  const uint32_t *wp = sk + skw;
+  const uint32_t *esc = wp + cw;
+  uint32_t invalid = 0;
 
-  // ranges
-  const uint32_t s = 32u * ((l * cw) / kWave), e = 32u * (((l + 1) * cw) / kWave);
-  for (uint32_t i = s >> 5; i < (e >> 5); i++) bm[i] = 0u;
-  __builtin_amdgcn_wave_barrier();
-  // phase 1: speculative decode of the own range
-  uint32_t pos = s, cnt = 0;
-  if (s < e) {
+  // this lane's range and its first codeword
+  uint32_t s = 0, e = 0, start = 0;
+  if (l < R) {
+    s = range_start(l, cw, R);
+    e = range_start(l + 1, cw, R);
+    start = s;
+    if (l > 0 && swd) {
+      const uint32_t bp = (l - 1) * swd, wi = bp >> 5, sh = bp & 31u;
+      uint32_t v = sk[wi] << sh;
+      if (sh + swd > 32u) v |= sk[wi + 1] >> (32u - sh);
+      start = s + (v >> (32u - swd));
+    }
+  }
+  // pass 1: count the codewords of the range
+  uint32_t pos = start, cnt = 0;
+  if (pos < e) {
     BitReader br;
-    br_init(br, wp, cw, s);
+    br_init(br, wp, cw, pos);
     while (pos < e) {
-      const uint32_t r = decode_one(T, br_peek(br));
-      const uint32_t ln = (r >> 16) & 31u;
-      atomicOr(&bm[pos >> 5], 1u << (pos & 31u));
+      const uint32_t ln = decode_len(T, br_peek(br));
       pos += ln;
       br_skip(br, ln);
       cnt++;
     }
   }
-  // exit1: where the first-pass path leaves the range (the true exit once a
-  // corrected path lands on a first-pass mark)
-  uint32_t start = s, exit1 = pos, exitp = pos;
-  __builtin_amdgcn_wave_barrier();
-  // phase 2: move wrong starts to the true ones
-  for (int it = 0; it <= kWave; it++) {
-    uint32_t tin = __shfl_up(exitp, 1, kWave);
-    if (l == 0) tin = 0;
-    const bool changed = tin != start;
-    if (!__ballot(changed)) break;
-    if (changed) {
-      uint32_t p = tin, c2 = 0;
-      bool synced = false;
-      if (p < e) {
-        BitReader br;
-        br_init(br, wp, cw, p);
-        while (p < e) {
-          if ((bm[p >> 5] >> (p & 31u)) & 1u) { synced = true; break; }
-          const uint32_t ln = (decode_one(T, br_peek(br)) >> 16) & 31u;
-          p += ln;
-          br_skip(br, ln);
-          c2++;
-        }
-      }
-      if (synced) {
-        uint32_t pc = __popc(bm[p >> 5] & (~0u << (p & 31u)));
-        for (uint32_t i = (p >> 5) + 1; i < (e >> 5); i++) pc += __popc(bm[i]);
-        cnt = c2 + pc;
-        exitp = exit1;
-      } else {
-        cnt = c2;
-        exitp = p;
-      }
-      start = tin;
-    }
-  }
+  // the codeword that ends a range must be where the next range's entry points
+  const uint32_t nstart = __shfl_down(start, 1, kWave);
+  if (l + 1 < R && pos != nstart) invalid = 1;
   const uint32_t total = wave_sum(cnt);
   if (total < len) { if (l == 0) *bad_flag = 1; return; }
   const uint32_t o = wave_incl_scan(cnt) - cnt;
-  __builtin_amdgcn_wave_barrier();
-  // phase 3: emit the owned symbols into the lane-chunk layout of reg
+  // pass 2: emit the symbols into the lane-chunk layout
   uint16_t *q16 = reinterpret_cast<uint16_t *>(reg);
-  auto qidx = [&](uint32_t el) -> uint32_t { return (el / E2) * 2u * E2 + E2 + (el % E2); };
-  uint32_t invalid = 0;
+  const uint32_t slot = E2 + 1;
+  auto qpos = [&](uint32_t el) -> uint32_t { return 2u * (el >> lg) * slot + E2 + (el & (E2 - 1)); };
+  auto fpos = [&](uint32_t el) -> uint32_t { return (el >> lg) * slot + (el & (E2 - 1)); };
   {
     uint32_t p = start, i = o;
     if (p < e && i < len) {
       BitReader br;
       br_init(br, wp, cw, p);
       while (p < e && i < len) {
-        const uint32_t r = decode_one(T, br_peek(br));
+        const uint32_t r = decode_sym(T, br_peek(br));
         const uint32_t ln = (r >> 16) & 31u;
         if (r & kLutInvalid) invalid = 1;
-        q16[qidx(i)] = (uint16_t)(r & 0xffffu);
+        q16[qpos(i)] = (uint16_t)(r & 0xffffu);
         p += ln;
         br_skip(br, ln);
         i++;
@@ -410,22 +390,22 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
   // phase 4: escapes, inverse prediction, reconstruction
   const uint32_t c0 = l * E2, c1 = min(len, c0 + E2);
   const uint32_t m = c1 > c0 ? c1 - c0 : 0u;
+  const uint16_t *qc = q16 + 2u * l * slot + E2;  // this lane's codes
   uint32_t ebase = 0;
   if (ne) {
     uint32_t ec = 0;
-    for (uint32_t j = c0; j < c1; j++) ec += q16[qidx(j)] == 0;
+    for (uint32_t j = 0; j < m; j++) ec += qc[j] == 0;
     const uint32_t etot = wave_sum(ec);
     if (etot != ne) invalid = 1;
     ebase = wave_incl_scan(ec) - ec;
   }
-  if (l == 0 && len && q16[qidx(0)] != (uint16_t)kRadius) invalid = 1;
-  const uint32_t *esc = wp + cw;
+  if (l == 0 && len && qc[0] != (uint16_t)kRadius) invalid = 1;
   // pass A: affine map of the lane's chunk (residual fed at level k)
   uint32_t s0 = 0, s1 = 0, s2 = 0;
   {
     uint32_t ei = ebase;
-    for (uint32_t j = c0; j < c1; j++) {
-      const uint32_t q = q16[qidx(j)];
+    for (uint32_t j = 0; j < m; j++) {
+      const uint32_t q = qc[j];
       uint32_t r;
       if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
       if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
@@ -453,10 +433,10 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
   {
     s2 = x1; s1 = x2; s0 = x3;
     uint32_t ei = ebase;
-    float *fo = reinterpret_cast<float *>(reg);
+    float *fo = reinterpret_cast<float *>(reg) + l * slot;
     const double step = st->step, mn = (double)st->mn;
-    for (uint32_t j = c0; j < c1; j++) {
-      const uint32_t q = q16[qidx(j)];
+    for (uint32_t j = 0; j < m; j++) {
+      const uint32_t q = qc[j];
       uint32_t r;
       if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
       if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
@@ -468,32 +448,33 @@ __device__ void decode_block(const DField &df, const DState *st, const DecTab &T
   }
   if (__ballot(invalid)) { if (l == 0) *bad_flag = 1; }
   __builtin_amdgcn_wave_barrier();
-  // coalesced store of the block
+  // coalesced store of the block, one float per lane per step
   const float *fo = reinterpret_cast<const float *>(reg);
   float *out = df.out + (uint64_t)b * S;
-  for (uint32_t j = 4 * l; j < len; j += 4 * kWave) {
-    if (j + 4 <= len) {
-      *reinterpret_cast<float4 *>(out + j) = *reinterpret_cast<const float4 *>(fo + j);
-    } else {
-      for (uint32_t i = j; i < len; i++) out[i] = fo[i];
-    }
-  }
+  for (uint32_t j = l; j < len; j += kWave) out[j] = fo[fpos(j)];
   __builtin_amdgcn_wave_barrier();
 }
 
-// dw waves per workgroup; dynamic LDS: lut | slow | dw regions of 4*Smax bytes
+// dw waves per workgroup.  Dynamic LDS: lut (4096 words) | first, base (32
+// words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
+// regions of 4 (smax + 64) bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
-                         uint32_t dw, uint32_t smax, uint32_t *ticket) {
+                         uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
-  uint32_t *s_slow = s_lut + (1u << kLutBits);
-  uint8_t *regs = reinterpret_cast<uint8_t *>(s_slow + kSlowWords);
+  uint32_t *s_first = s_lut + (1u << kLutBits);
+  uint32_t *s_base = s_first + 32;
+  uint64_t *s_limit = reinterpret_cast<uint64_t *>(s_base + 32);
+  uint16_t *s_syms = reinterpret_cast<uint16_t *>(s_limit + 32);
+  uint8_t *regs = reinterpret_cast<uint8_t *>(s_syms) + ((2u * symcap + 15u) & ~15u);
   __shared__ uint32_t s_task;
   const int t = threadIdx.x;
   const uint32_t w = t / kWave;
   const int np = 3 * nf;
   const uint32_t T = tbase[np];
+  uint32_t lg = 0;
   int cur = -1;
+  bool syms_lds = false;
   for (;;) {
     if (t == 0) s_task = atomicAdd(ticket, 1u);
     __syncthreads();
@@ -514,22 +495,33 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
       const uint32_t *gl = df.lut + (uint64_t)k * (1u << kLutBits);
       for (uint32_t i = t; i < (1u << kLutBits); i += blockDim.x) s_lut[i] = gl[i];
       const uint32_t *gs = df.slow + (uint64_t)k * kSlowWords;
-      for (uint32_t i = t; i < (uint32_t)kSlowWords; i += blockDim.x) s_slow[i] = gs[i];
+      for (uint32_t i = t; i < 32u; i += blockDim.x) {
+        s_first[i] = gs[i];
+        s_base[i] = gs[32 + i];
+        s_limit[i] = (uint64_t)gs[64 + 2 * i] | ((uint64_t)gs[64 + 2 * i + 1] << 32);
+      }
+      const uint32_t ns = st->nsym[k];
+      syms_lds = ns <= symcap;
+      if (syms_lds) {
+        const uint16_t *gsy = df.syms + (uint64_t)k * kNSyms;
+        for (uint32_t i = t; i < ns; i += blockDim.x) s_syms[i] = gsy[i];
+      }
+      lg = 31u - __clz(st->S / kWave);
       __syncthreads();
       cur = pair;
     }
     DecTab T2;
     T2.lut = s_lut;
-    T2.first = s_slow;
-    T2.base = s_slow + 32;
-    T2.limit = s_slow + 64;
-    T2.syms = df.syms + (uint64_t)k * kNSyms;
+    T2.first = s_first;
+    T2.base = s_base;
+    T2.limit = s_limit;
+    T2.syms = syms_lds ? s_syms : df.syms + (uint64_t)k * kNSyms;
     T2.maxlen = st->maxlen[k];
     const uint32_t idx = (task - tbase[pair]) * dw + w;
     if (idx < st->grp_count[k]) {
       const uint32_t b = df.order[st->grp_start[k] + idx];
       int bad = 0;
-      decode_block(df, st, T2, b, regs + (uint64_t)w * 4u * smax, &bad);
+      decode_block(df, st, T2, b, regs + (uint64_t)w * 4u * (smax + 64u), lg, &bad);
       if (bad && lane_id() == 0) atomicCAS((int *)&df.st->status, 0, SZNB_ECORRUPT);
     }
   }

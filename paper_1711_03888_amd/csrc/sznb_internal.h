@@ -91,6 +91,27 @@ struct alignas(64) GCtl {
   uint32_t pad[15];
 };
 
+// Skip table of a block: its code words are cut into R word-aligned ranges
+// (range l starts at bit 32 floor(l cw / R), R = min(64, max(1, cw / 8)));
+// for each range after the first the stream stores, in w = bitlen(maxlen-1)
+// bits MSB first ahead of the code words, the distance from the range start
+// to the first codeword starting at or after it.
+__host__ __device__ inline uint32_t n_ranges(uint32_t cw) {
+  const uint32_t r = cw / 8;
+  return r < 1 ? 1u : (r > 64 ? 64u : r);
+}
+__host__ __device__ inline uint32_t skip_width(uint32_t maxlen) {
+  uint32_t w = 0;
+  while ((1u << w) < maxlen) w++;
+  return w;
+}
+__host__ __device__ inline uint32_t skip_words(uint32_t cw, uint32_t maxlen) {
+  return ((n_ranges(cw) - 1) * skip_width(maxlen) + 31) / 32;
+}
+__host__ __device__ inline uint32_t range_start(uint32_t l, uint32_t cw, uint32_t R) {
+  return 32u * (uint32_t)(((uint64_t)l * cw) / R);
+}
+
 // predictor that histogram slot s of a field codes
 __host__ __device__ inline int slot_pred(int policy, int s) { return policy >= 2 ? s : policy; }
 

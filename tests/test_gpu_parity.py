@@ -155,6 +155,14 @@ def test_corrupt_streams_rejected():
     bad[h["off_cwords"] + 1] = 0xFF
     with pytest.raises(sznb.SznbError):
         sznb.decompress(bad, x.size)
+    # a wrong skip-table entry breaks the chain of range entry points
+    bad = good.clone()
+    bad[h["off_payload"] + 3] ^= 0x10
+    with pytest.raises(sznb.SznbError) as e:
+        sznb.decompress(bad, x.size)
+    assert e.value.code == sznb.ECORRUPT
+    with pytest.raises(oracle.OracleError):
+        oracle.decompress(bytes(bad.cpu().numpy()))
 
 
 def test_batch_equals_single():

@@ -269,10 +269,18 @@ def _parse_and_decode(stream):
     for b in range(nb):
         m = min(S, n - b * S)
         table = tables[int(pred[b])]
+        maxlen = h["max_len"][int(pred[b])]
+        # skip table: R ranges of the code words, one width-w entry per range after the first
+        R = max(1, min(64, cw[b] // 8))
+        wdt = (maxlen - 1).bit_length()
+        skw = ((R - 1) * wdt + 31) // 32
+        sbits = "".join(format(int(v), "032b") for v in words[w:w + skw])
+        w += skw
         bits = "".join(format(int(v), "032b") for v in words[w:w + cw[b]])
         esc = [int(v) for v in words[w + cw[b]:w + cw[b] + ne[b]].astype(np.int32)]
-        pos = 0
+        pos, starts = 0, []
         for _ in range(m):
+            starts.append(pos)
             cur = ""
             while cur not in table:
                 cur += bits[pos]
@@ -280,6 +288,11 @@ def _parse_and_decode(stream):
             sy = table[cur]
             out.append(esc.pop(0) if sy == 0 else sy - 32768)
         assert not esc and set(bits[pos:]) <= {"0"}
+        for l in range(1, R):
+            st = 32 * ((l * cw[b]) // R)
+            first = next(p for p in starts if p >= st)
+            assert int(sbits[(l - 1) * wdt:l * wdt] or "0", 2) == first - st
+        assert set(sbits[(R - 1) * wdt:]) <= {"0"}
         w += cw[b] + ne[b]
     return np.array(out, np.int64), pred
 
