@@ -373,14 +373,15 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * nf), dim3(kThreads), 0, stream, D);
   // waves per workgroup and symbol table placement: most resident waves per
   // CU under the LDS of a CU (tables once per workgroup, one region per wave)
-  const size_t lds_cu = dv->lds_per_block ? dv->lds_per_block : 65536;
+  // (1 KiB stays free for the kernel's static LDS and alignment)
+  const size_t lds_cu = (dv->lds_per_block ? dv->lds_per_block : 65536) - 1024;
   const size_t tables = 4ull * (1u << kLutBits) + 4ull * 64 + 8ull * 32;
   uint32_t symcap = nsym_max;
-  const size_t per_wave = 4ull * (smax + 64);
+  const size_t per_wave = 2ull * (smax + smax / 32);
   if (tables + ((2ull * symcap + 15) & ~15ull) + per_wave > lds_cu) symcap = 0;
   const size_t symb = (2ull * symcap + 15) & ~15ull;
   uint32_t dw = 1, best = 0;
-  for (uint32_t cand = 1; cand <= 8; cand++) {
+  for (uint32_t cand = 1; cand <= 16; cand++) {
     const size_t need = tables + symb + cand * per_wave;
     if (need > lds_cu) break;
     const uint32_t waves = cand * (uint32_t)(lds_cu / need);

@@ -312,17 +312,19 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
 // One wave decodes block b of a stream and stores its floats.
 // Lane l < R decodes the codewords starting in range l of the block's code
 // bits, from the first codeword the skip table points at: one pass counts
-// them, a second writes them after the counts of the lanes before it.
-// Region layout (4 (S + 64) bytes): lane l owns float slots
-// [l (E2+1), l (E2+1) + E2) (E2 = S/64; the one-slot skew keeps the 64 lanes
-// on distinct LDS banks), and the u16 codes of its chunk sit in the upper
-// half of its slot, so writing float i only overwrites codes it has read.
+// them, a second writes their codes after the counts of the lanes before it
+// into the wave's LDS region (u16 per element, one padding word per 64
+// elements keeps concurrent lanes on different banks).  The inverse
+// prediction then runs row by row: each 64-element row is integrated with
+// one (LV), two (LCF) or three (QCF) DPP wave scans carried across rows, and
+// the reconstructed floats are stored straight from registers, coalesced.
+__device__ __forceinline__ uint32_t qaddr(uint32_t e) { return e + 2u * (e >> 6); }
+
 __device__ __forceinline__ void decode_block(const DField &df, const DState *st, const DecTab &T, uint32_t b,
-                                             uint8_t *reg, uint32_t lg, int *bad_flag) {
+                                             uint16_t *q16, int *bad_flag) {
   const uint32_t l = lane_id();
   const uint8_t *in = df.in;
   const uint32_t S = st->S;
-  const uint32_t E2 = 1u << lg;
   const uint32_t len = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
   const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
   const uint32_t ne = rd16(in, st->off_nesc + 2ull * b);
@@ -334,6 +336,13 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
   const uint32_t *esc = wp + cw;
   uint32_t invalid = 0;
 
+  // bring the block's words into cache with a coalesced sweep, so that the
+  // lanes' sequential readers below do not each wait on memory
+  {
+    uint32_t sink = 0;
+    for (uint32_t i = l; i < skw + cw; i += kWave) sink |= sk[i];
+    asm volatile("" ::"v"(sink));  // the loaded values count as used
+  }
   // this lane's range and its first codeword
   uint32_t s = 0, e = 0, start = 0;
   if (l < R) {
@@ -364,12 +373,8 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
   if (l + 1 < R && pos != nstart) invalid = 1;
   const uint32_t total = wave_sum(cnt);
   if (total < len) { if (l == 0) *bad_flag = 1; return; }
-  const uint32_t o = wave_incl_scan(cnt) - cnt;
-  // pass 2: emit the symbols into the lane-chunk layout
-  uint16_t *q16 = reinterpret_cast<uint16_t *>(reg);
-  const uint32_t slot = E2 + 1;
-  auto qpos = [&](uint32_t el) -> uint32_t { return 2u * (el >> lg) * slot + E2 + (el & (E2 - 1)); };
-  auto fpos = [&](uint32_t el) -> uint32_t { return (el >> lg) * slot + (el & (E2 - 1)); };
+  const uint32_t o = wave_scan_dpp(cnt) - cnt;
+  // pass 2: emit the codes
   {
     uint32_t p = start, i = o;
     if (p < e && i < len) {
@@ -379,7 +384,7 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
         const uint32_t r = decode_sym(T, br_peek(br));
         const uint32_t ln = (r >> 16) & 31u;
         if (r & kLutInvalid) invalid = 1;
-        q16[qpos(i)] = (uint16_t)(r & 0xffffu);
+        q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
         p += ln;
         br_skip(br, ln);
         i++;
@@ -387,77 +392,52 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
     }
   }
   __builtin_amdgcn_wave_barrier();
-  // phase 4: escapes, inverse prediction, reconstruction
-  const uint32_t c0 = l * E2, c1 = min(len, c0 + E2);
-  const uint32_t m = c1 > c0 ? c1 - c0 : 0u;
-  const uint16_t *qc = q16 + 2u * l * slot + E2;  // this lane's codes
-  uint32_t ebase = 0;
-  if (ne) {
-    uint32_t ec = 0;
-    for (uint32_t j = 0; j < m; j++) ec += qc[j] == 0;
-    const uint32_t etot = wave_sum(ec);
-    if (etot != ne) invalid = 1;
-    ebase = wave_incl_scan(ec) - ec;
-  }
-  if (l == 0 && len && qc[0] != (uint16_t)kRadius) invalid = 1;
-  // pass A: affine map of the lane's chunk (residual fed at level k)
-  uint32_t s0 = 0, s1 = 0, s2 = 0;
-  {
-    uint32_t ei = ebase;
-    for (uint32_t j = 0; j < m; j++) {
-      const uint32_t q = qc[j];
-      uint32_t r;
-      if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
-      if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
-      else if (k == 1) { s1 += r; s0 += s1; }
-      else s0 += r;
-    }
-  }
-  // wave exclusive scan of chunk maps (m, R1, R2, R3) = (m, s2, s1, s0)
-  uint32_t tm = m, R1 = s2, R2 = s1, R3 = s0;
-#pragma unroll
-  for (int dd = 1; dd < kWave; dd <<= 1) {
-    const uint32_t am = __shfl_up(tm, dd, kWave), a1 = __shfl_up(R1, dd, kWave);
-    const uint32_t a2 = __shfl_up(R2, dd, kWave), a3 = __shfl_up(R3, dd, kWave);
-    if (l >= (uint32_t)dd) {
-      const uint32_t mb = tm, T2 = (uint32_t)(((uint64_t)mb * (mb + 1)) >> 1);
-      R3 = a3 + mb * a2 + T2 * a1 + R3;
-      R2 = a2 + mb * a1 + R2;
-      R1 = a1 + R1;
-      tm = am + mb;
-    }
-  }
-  uint32_t x1 = __shfl_up(R1, 1, kWave), x2 = __shfl_up(R2, 1, kWave), x3 = __shfl_up(R3, 1, kWave);
-  if (l == 0) { x1 = 0; x2 = 0; x3 = 0; }
-  // pass B: states from the prefix, reconstructed floats written in place
-  {
-    s2 = x1; s1 = x2; s0 = x3;
-    uint32_t ei = ebase;
-    float *fo = reinterpret_cast<float *>(reg) + l * slot;
-    const double step = st->step, mn = (double)st->mn;
-    for (uint32_t j = 0; j < m; j++) {
-      const uint32_t q = qc[j];
-      uint32_t r;
-      if (q == 0) { r = ei < ne ? esc[ei] : 0u; ei++; } else r = q - (uint32_t)kRadius;
-      if (k == 2) { s2 += r; s1 += s2; s0 += s1; }
-      else if (k == 1) { s1 += r; s0 += s1; }
-      else s0 += r;
-      const int32_t p = (int32_t)((uint32_t)p0 + s0);
-      fo[j] = (float)fma((double)p, step, mn);
-    }
-  }
-  if (__ballot(invalid)) { if (l == 0) *bad_flag = 1; }
-  __builtin_amdgcn_wave_barrier();
-  // coalesced store of the block, one float per lane per step
-  const float *fo = reinterpret_cast<const float *>(reg);
+  // inverse prediction and reconstruction, one row of 64 values at a time
+  const uint64_t lt = l ? (~0ull >> (64 - l)) : 0ull;
+  uint32_t c0 = 0, c1 = 0, c2 = 0, ebase = 0;
+  const double step = st->step, mn = (double)st->mn;
   float *out = df.out + (uint64_t)b * S;
-  for (uint32_t j = l; j < len; j += kWave) out[j] = fo[fpos(j)];
+  if (l == 0 && len && q16[0] != (uint16_t)kRadius) invalid = 1;
+  for (uint32_t row = 0; row < len; row += kWave) {
+    const uint32_t el = row + l;
+    const bool valid = el < len;
+    const uint32_t q = valid ? q16[qaddr(el)] : (uint32_t)kRadius;
+    uint32_t r = q - (uint32_t)kRadius;
+    const uint64_t em = __ballot(valid && q == 0u);
+    if (em) {
+      if (valid && q == 0u) {
+        const uint32_t ei = ebase + (uint32_t)__popcll(em & lt);
+        r = ei < ne ? esc[ei] : 0u;
+      }
+      ebase += (uint32_t)__popcll(em);
+    }
+    uint32_t x;
+    if (k == 0) {
+      x = wave_scan_dpp(r) + c0;
+      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+    } else if (k == 1) {
+      const uint32_t y = wave_scan_dpp(r) + c1;
+      c1 = (uint32_t)__builtin_amdgcn_readlane((int)y, 63);
+      x = wave_scan_dpp(y) + c0;
+      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+    } else {
+      const uint32_t z = wave_scan_dpp(r) + c2;
+      c2 = (uint32_t)__builtin_amdgcn_readlane((int)z, 63);
+      const uint32_t y = wave_scan_dpp(z) + c1;
+      c1 = (uint32_t)__builtin_amdgcn_readlane((int)y, 63);
+      x = wave_scan_dpp(y) + c0;
+      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+    }
+    if (valid) out[el] = (float)fma((double)(int32_t)((uint32_t)p0 + x), step, mn);
+  }
+  if (ebase != ne) invalid = 1;
+  if (__ballot(invalid)) { if (l == 0) *bad_flag = 1; }
   __builtin_amdgcn_wave_barrier();
 }
 
 // dw waves per workgroup.  Dynamic LDS: lut (4096 words) | first, base (32
 // words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
-// regions of 4 (smax + 64) bytes.
+// code regions of 2 (smax + smax/32) bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
                          uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -472,7 +452,6 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
   const uint32_t w = t / kWave;
   const int np = 3 * nf;
   const uint32_t T = tbase[np];
-  uint32_t lg = 0;
   int cur = -1;
   bool syms_lds = false;
   for (;;) {
@@ -506,7 +485,6 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
         const uint16_t *gsy = df.syms + (uint64_t)k * kNSyms;
         for (uint32_t i = t; i < ns; i += blockDim.x) s_syms[i] = gsy[i];
       }
-      lg = 31u - __clz(st->S / kWave);
       __syncthreads();
       cur = pair;
     }
@@ -521,7 +499,7 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     if (idx < st->grp_count[k]) {
       const uint32_t b = df.order[st->grp_start[k] + idx];
       int bad = 0;
-      decode_block(df, st, T2, b, regs + (uint64_t)w * 4u * (smax + 64u), lg, &bad);
+      decode_block(df, st, T2, b, reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * (smax + smax / 32u)), &bad);
       if (bad && lane_id() == 0) atomicCAS((int *)&df.st->status, 0, SZNB_ECORRUPT);
     }
   }
