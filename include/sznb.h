@@ -111,6 +111,30 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
 
 const char *sznb_strerror(int status);
 
+/* ---- molecular-dynamics snapshots: the paper's three modes (Sec. 5.2, Sec. 6)
+ * md_mode 0 best_speed:       SZ-LV on every field in stored order;
+ * md_mode 1 best_tradeoff:    particles reordered by a stable sort of their
+ *                             R-index without its 6 least significant 3-bit
+ *                             digits inside 16384-particle segments (Table 5),
+ *                             then SZ-LV on every field;
+ * md_mode 2 best_compression: full R-index sort; the sorted coordinate keys
+ *                             coded CPC2000-style (Rice-coded deltas), the
+ *                             velocities by SZ-LV in the same order.
+ * h_fields: 3 coordinate fields (x, y, z), optionally followed by 3 velocity
+ * fields, each of n values (device pointers, 16-byte aligned).  eb_rel is the
+ * value-range-relative bound of every field.  The particles come back from
+ * sznb_md_decompress in the stored order of the stream (reordered for modes 1
+ * and 2: no index is kept, every field is permuted the same way); the
+ * permutation is written to d_perm_or_null when given.  Both calls wait for
+ * the stream and return the first device status. */
+uint64_t sznb_md_workspace_bytes(int nf, uint64_t n);
+uint64_t sznb_md_bound(int nf, uint64_t n);
+int sznb_md_compress(int nf, const float *const *h_fields, uint64_t n, double eb_rel, int md_mode,
+                     void *d_out, uint64_t out_cap, uint64_t *d_out_len, uint32_t *d_perm_or_null,
+                     void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+int sznb_md_decompress(const void *d_in, uint64_t in_len, int nf, uint64_t n, float *const *h_outs,
+                       void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
 /* Measurement hooks.  sznb_profile(1) clears the record and brackets every
  * later kernel launch with a pair of HIP events on the launch stream;
  * sznb_profile(0) stops recording.  sznb_profile_summary() waits for the

@@ -59,6 +59,8 @@ def lib():
         L.sznbref_canonical.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.sznbref_reconstruct.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_float]
         L.sznbref_reconstruct.restype = ctypes.c_float
+        L.sznbref_reconstruct_array.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_float,
+                                                ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -180,6 +182,13 @@ def canonical(lengths):
 
 def reconstruct(p: int, step: float, mn: float) -> float:
     return float(lib().sznbref_reconstruct(int(p), step, mn))
+
+
+def reconstruct_array(p, step: float, mn: float) -> np.ndarray:
+    p = np.ascontiguousarray(p, dtype=np.int64)
+    out = np.zeros(p.size, np.float32)
+    lib().sznbref_reconstruct_array(p.ctypes.data, p.size, step, mn, out.ctypes.data)
+    return out
 
 
 # ------------------------------------------------------------ stream parsing

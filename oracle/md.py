@@ -1,0 +1,267 @@
+"""Oracle of the molecular-dynamics modes (test infrastructure only).
+
+The paper's three modes for MD snapshots (Sec. 5.2 and Sec. 6):
+
+* best_speed       = SZ-LV on every field in stored order;
+* best_tradeoff    = SZ-LV-PRX: reorder the particles by a partial radix
+  sort of their R-index within fixed index segments, then SZ-LV;
+* best_compression = SZ-CPC2000: CPC2000 coding of the sorted coordinate
+  keys, SZ-LV on the velocities reordered the same way.
+
+R-index (Sec. 5.2, after CPC2000 in Sec. 2): the coordinates are turned into
+integers by the error bound and their binary digits interleaved.  Partial
+radix sort (Sec. 5.2): LSD radix on 3-bit digits that skips the k least
+significant digits, i.e. a stable sort by key >> 3k.  Sorting reorders every
+array the same way and no index is stored (Sec. 5.2).
+
+Readings where the paper is silent:
+* integers = the compressor's own lattice index of each coordinate field
+  (range, bound and guard exactly as in sznb_oracle.c), so decoding a key
+  gives back lattice points within the bound;
+* B = max over the three coordinates of bitlen(P_c) bits per coordinate, at
+  most 21 (a 63-bit key); digit j of the key holds (x_j, y_j, z_j), x highest;
+* segments are index ranges of 16384 particles (Tables 4 and 5);
+* CPC2000's "adaptive variable-length encoding with status bits" (Sec. 2,
+  Sec. 5.2) is read as Rice coding of the key deltas of each sorted segment:
+  parameter r = argmin_r sum(floor(d / 2^r) + 1 + r) (ties to the smaller r),
+  a delta coded as floor(d / 2^r) one-bits, a zero, then the r low bits; a
+  quotient of 32 or more is coded as 32 one-bits followed by the raw delta in
+  3B bits.  PARITY UNPINNED against the paper: its exact variable-length code
+  is not given; the tests pin the code by lossless round trip and by
+  independent decoding.
+"""
+from __future__ import annotations
+
+import struct
+
+import numpy as np
+
+from . import EB_REL, LV, compress, decompress, lattice, params, reconstruct_array
+
+SEG = 16384
+SPEED, TRADEOFF, COMPRESSION = 0, 1, 2
+PRX_IGNORED = 6  # Table 5: segment 16384, six ignored 3-bit digits
+CPC_ESC_Q = 32
+
+
+def bits_per_coord(coords, eb_rel):
+    ps = [params(c, eb_rel)["P"] for c in coords]
+    B = max(int(P).bit_length() for P in ps)
+    return max(B, 1)
+
+
+def rindex_keys(coords, eb_rel):
+    """Interleaved lattice keys of the particles (x bit highest in each digit)."""
+    B = bits_per_coord(coords, eb_rel)
+    if B > 21:
+        raise ValueError("lattice too fine for a 63-bit key")
+    ps = [lattice(c, eb_rel).astype(np.uint64) for c in coords]
+    key = np.zeros(ps[0].size, np.uint64)
+    for j in range(B):
+        for c in range(3):
+            bit = (ps[c] >> np.uint64(j)) & np.uint64(1)
+            key |= bit << np.uint64(3 * j + (2 - c))
+    return key, B
+
+
+def deinterleave(key, B):
+    out = [np.zeros(key.size, np.int64) for _ in range(3)]
+    for j in range(B):
+        for c in range(3):
+            out[c] |= ((key >> np.uint64(3 * j + (2 - c))) & np.uint64(1)).astype(np.int64) << j
+    return out
+
+
+def segment_order(key, k):
+    """Stable sort of each segment by key >> 3k (LSD radix from digit k)."""
+    n = key.size
+    perm = np.empty(n, np.int64)
+    sk = key >> np.uint64(3 * k)
+    for s in range(0, n, SEG):
+        perm[s:s + SEG] = s + np.argsort(sk[s:s + SEG], kind="stable")
+    return perm
+
+
+# ----------------------------------------------------------- CPC2000 keys
+
+def rice_parameter(deltas, keybits):
+    best, best_cost = 0, None
+    for r in range(0, keybits + 1):
+        q = deltas >> np.uint64(r)
+        esc = q >= CPC_ESC_Q
+        cost = int(np.where(esc, CPC_ESC_Q + keybits, q.astype(np.int64) + 1 + r).sum())
+        if best_cost is None or cost < best_cost:
+            best, best_cost = r, cost
+    return best
+
+
+def pack_fields(values, nbits):
+    """MSB-first concatenation of (value, width) fields into u32 words."""
+    values = np.asarray(values, np.uint64)
+    nbits = np.asarray(nbits, np.int64)
+    total = int(nbits.sum())
+    idx = np.repeat(np.arange(values.size), nbits)
+    start = np.concatenate([[0], np.cumsum(nbits)[:-1]])
+    within = np.arange(total) - np.repeat(start, nbits)
+    shift = (np.repeat(nbits, nbits) - 1 - within).astype(np.uint64)
+    bits = ((values[idx] >> shift) & np.uint64(1)).astype(np.uint8)
+    bits = np.concatenate([bits, np.zeros(-total % 32, np.uint8)])
+    words = np.packbits(bits).view(">u4").astype(np.uint32)
+    return words, total
+
+
+def cpc_encode_segment(keys_sorted, keybits):
+    """First key raw, 6-bit Rice parameter, then the Rice-coded deltas."""
+    d = np.diff(keys_sorted.astype(np.uint64))
+    r = rice_parameter(d, keybits) if d.size else 0
+    q = (d >> np.uint64(r)).astype(np.int64)
+    esc = q >= CPC_ESC_Q
+    qq = np.where(esc, 0, q)
+    # per delta: unary part (q ones then a zero, or 32 ones), then r low bits
+    # or the raw delta
+    unary_v = np.where(esc, np.uint64((1 << CPC_ESC_Q) - 1), (np.uint64(1) << (qq + 1).astype(np.uint64)) - np.uint64(2))
+    unary_n = np.where(esc, CPC_ESC_Q, qq + 1)
+    tail_v = np.where(esc, d, d & np.uint64((1 << r) - 1))
+    tail_n = np.where(esc, keybits, r)
+    vals = np.empty(2 + 2 * d.size, np.uint64)
+    lens = np.empty(2 + 2 * d.size, np.int64)
+    vals[0], lens[0] = np.uint64(keys_sorted[0]), keybits
+    vals[1], lens[1] = np.uint64(r), 6
+    vals[2::2], lens[2::2] = unary_v, unary_n
+    vals[3::2], lens[3::2] = tail_v, tail_n
+    return pack_fields(vals, lens)
+
+
+def cpc_decode_segment(words, count, keybits):
+    bits = np.unpackbits(words.astype(">u4").view(np.uint8))
+    pos = 0
+
+    def take(nb):
+        nonlocal pos
+        v = 0
+        for _ in range(nb):
+            v = (v << 1) | int(bits[pos])
+            pos += 1
+        return v
+
+    keys = [take(keybits)]
+    r = take(6)
+    for _ in range(count - 1):
+        q = 0
+        while q < CPC_ESC_Q and bits[pos] == 1:
+            q += 1
+            pos += 1
+        if q == CPC_ESC_Q:
+            d = take(keybits)
+        else:
+            pos += 1  # the terminating zero
+            d = (q << r) | take(r)
+        keys.append(keys[-1] + d)
+    return np.array(keys, np.uint64)
+
+
+# --------------------------------------------------------------- container
+
+MD_MAGIC = b"SZMD"
+MD_HDR = 96
+
+
+CP_FMT = "<4sHBBQIII6f3d3d"
+
+
+def _coord_stream(coords, eb_rel, perm_keys, B):
+    """CPC2000 coordinate stream: header, per-segment bit counts, payload."""
+    n = perm_keys.size
+    keybits = 3 * B
+    nseg = (n + SEG - 1) // SEG
+    pr = [params(c, eb_rel) for c in coords]
+    seg_words, seg_bits = [], []
+    for s in range(nseg):
+        w, nb = cpc_encode_segment(perm_keys[s * SEG:(s + 1) * SEG], keybits)
+        seg_words.append(w)
+        seg_bits.append(nb)
+    head = struct.pack(CP_FMT, b"SZCP", 1, B, 0, n, nseg, SEG, keybits,
+                       pr[0]["mn"], pr[0]["mx"], pr[1]["mn"], pr[1]["mx"], pr[2]["mn"], pr[2]["mx"],
+                       pr[0]["eb_abs"], pr[1]["eb_abs"], pr[2]["eb_abs"],
+                       pr[0]["step"], pr[1]["step"], pr[2]["step"])
+    head += b"\0" * (-len(head) % 8)
+    tab = np.array(seg_bits, np.uint32).tobytes()
+    tab += b"\0" * (-len(tab) % 8)
+    body = b"".join(w.astype("<u4").tobytes() for w in seg_words)
+    return head + tab + body
+
+
+def compress_md(fields, eb_rel, md_mode):
+    """fields: 3 coordinate arrays, optionally followed by 3 velocity arrays.
+    Returns (container bytes, permutation applied to the particles)."""
+    fields = [np.ascontiguousarray(f, np.float32) for f in fields]
+    nf = len(fields)
+    n = fields[0].size
+    if nf not in (3, 6) or any(f.size != n for f in fields):
+        raise ValueError("3 or 6 equal-length fields")
+    mode_lv = LV | EB_REL
+    if md_mode == SPEED:
+        perm = np.arange(n)
+        k = 0
+    else:
+        key, B = rindex_keys(fields[:3], eb_rel)
+        k = PRX_IGNORED if md_mode == TRADEOFF else 0
+        perm = segment_order(key, k)
+    subs = []
+    if md_mode == COMPRESSION:
+        subs.append(_coord_stream(fields[:3], eb_rel, key[perm], B))
+        for f in fields[3:]:
+            subs.append(compress(f[perm], eb_rel, mode_lv))
+    else:
+        for f in fields:
+            subs.append(compress(f[perm], eb_rel, mode_lv))
+    offs, o = [], MD_HDR
+    for sb in subs:
+        offs.append(o)
+        o += len(sb) + (-len(sb) % 8)
+    offs += [0] * (6 - len(offs))
+    head = struct.pack("<4sHBBQIIQ6Q", MD_MAGIC, 1, md_mode, nf, n, SEG, k, o, *offs)
+    head += b"\0" * (MD_HDR - len(head))
+    body = b"".join(sb + b"\0" * (-len(sb) % 8) for sb in subs)
+    return head + body, perm
+
+
+def decompress_md(blob):
+    magic, ver, md_mode, nf, n, seg, k, total, *offs = struct.unpack_from("<4sHBBQIIQ6Q", blob, 0)
+    assert magic == MD_MAGIC and ver == 1
+    out = []
+    nsub = nf if md_mode != COMPRESSION else nf - 2
+    ends = [offs[i + 1] if i + 1 < nsub else total for i in range(nsub)]
+    subs = [blob[offs[i]:ends[i]] for i in range(nsub)]
+    if md_mode == COMPRESSION:
+        out += decode_coord_stream(subs[0])
+        for sb in subs[1:]:
+            out.append(decompress(sb))
+    else:
+        for sb in subs:
+            out.append(decompress(sb))
+    return out
+
+
+def decode_coord_stream(sb):
+    vals = struct.unpack_from(CP_FMT, sb, 0)
+    magic, ver, B, _, n, nseg, seg, keybits = vals[:8]
+    mnmx = vals[8:14]
+    steps = vals[17:20]
+    assert magic == b"SZCP" and ver == 1
+    hlen = struct.calcsize(CP_FMT)
+    hlen += -hlen % 8
+    seg_bits = np.frombuffer(sb, np.uint32, count=nseg, offset=hlen)
+    o = hlen + 4 * nseg
+    o += -o % 8
+    keys = []
+    for s in range(nseg):
+        nw = (int(seg_bits[s]) + 31) // 32
+        words = np.frombuffer(sb, "<u4", count=nw, offset=o)
+        o += 4 * nw
+        cnt = min(seg, n - s * seg)
+        keys.append(cpc_decode_segment(words, cnt, keybits))
+    key = np.concatenate(keys)
+    ps = deinterleave(key, B)
+    # reconstruction x~ = fl32(fma(p, step, mn)) per coordinate
+    return [reconstruct_array(ps[c], steps[c], mnmx[2 * c]) for c in range(3)]

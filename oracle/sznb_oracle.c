@@ -806,6 +806,15 @@ int sznbref_canonical(const uint8_t *len, uint32_t *code, uint16_t *order)
     return m;
 }
 
+void sznbref_reconstruct_array(const int64_t *p, uint64_t n, double step, float mn, float *out)
+{
+    params_t q;
+    memset(&q, 0, sizeof q);
+    q.step = step;
+    q.mn = mn;
+    for (uint64_t i = 0; i < n; i++) out[i] = reconstruct((int32_t)p[i], &q);
+}
+
 float sznbref_reconstruct(int32_t pi, double step, float mn)
 {
     params_t p;

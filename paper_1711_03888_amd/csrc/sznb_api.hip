@@ -25,6 +25,21 @@ __global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int);
 __global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *);
 
+struct MdCtl;
+__global__ void md_bits(const FState *, const FState *, const FState *, MdCtl *, uint64_t);
+__global__ void md_keys(const float *, const float *, const float *, uint64_t, const FState *, const FState *,
+                        const FState *, const MdCtl *, uint64_t *, uint32_t *);
+__global__ void md_sort(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint64_t, uint32_t, const MdCtl *);
+__global__ void md_gather(const float *, float *, const uint32_t *, uint64_t, const MdCtl *);
+__global__ void cpc_count(const uint64_t *, uint64_t, const MdCtl *, uint32_t *, uint32_t *);
+__global__ void cpc_offsets(const uint32_t *, uint32_t, uint64_t, MdCtl *, const FState *, const FState *,
+                            const FState *, uint8_t *, uint32_t *);
+__global__ void cpc_pack(const uint64_t *, uint64_t, const MdCtl *, const uint32_t *, const uint32_t *,
+                         const uint32_t *, uint8_t *);
+__global__ void cpc_decode(const uint8_t *, uint64_t, uint64_t, float *, float *, float *, int *);
+__global__ void md_assemble(uint8_t *, uint64_t, uint64_t *, const uint8_t *const *, const uint64_t *, int, int, int,
+                            uint64_t, uint32_t, const MdCtl *, int *);
+
 constexpr uint64_t kStateStride = 256;
 
 // ------------------------------------------------------------ profiling
@@ -207,7 +222,7 @@ static void launch_E(bool quant, const Launch &P, hipStream_t s, int grid) {
 // waves per CU used for the persistent per-block kernels (tunable)
 static int g_wg_per_cu = 8;
 
-static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv) {
+static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params_only = false) {
   const CField *F = reinterpret_cast<const CField *>(P.ws + P.L.fields);
   const uint64_t *fb0 = reinterpret_cast<const uint64_t *>(P.ws + P.L.fb0);
   GCtl *gc = reinterpret_cast<GCtl *>(P.ws + P.L.gctl);
@@ -219,6 +234,7 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv) {
   if (gper > 8) gper &= ~7;  // multiple of the XCD count keeps a block on one XCD across passes
   if (tb) SZNB_LAUNCH("k_range", k_range, dim3(gper), dim3(kThreads), 0, s, F, P.nf, fb0, tb);
   SZNB_LAUNCH("k_params", k_params, dim3(P.nf), dim3(kThreads), 0, s, F);
+  if (params_only) return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
   if (tb) launch_E(true, P, s, gper);
   SZNB_LAUNCH("k_huff", k_huff, dim3(P.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host());
   SZNB_LAUNCH("k_books", k_books, dim3(P.nf), dim3(kThreads), 0, s, F);
@@ -229,7 +245,8 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv) {
 
 static int compress_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
                          const uint32_t *mode, void *const *outs, const uint64_t *caps, uint64_t *d_lens,
-                         bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+                         bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream,
+                         bool params_only = false) {
   if (nf <= 0 || !d_ws) return SZNB_EINVAL;
   DevInfo *dv;
   int rc = dev_init(&dv);
@@ -288,7 +305,7 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
   P.nslots = L.nslots;
   P.ws = ws;
   P.L = L;
-  return compress_run(P, stream, dv);
+  return compress_run(P, stream, dv, params_only);
 }
 
 // ---------------------------------------------------------- decompress
@@ -402,6 +419,223 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
+// ------------------------------------------------------------ MD modes
+
+constexpr uint32_t kMdSeg = 16384;
+constexpr uint32_t kMdPrx = 6;  // Table 5: six ignored 3-bit digits
+constexpr uint32_t kMdMode = SZNB_PRED_LV | SZNB_EB_REL;
+
+struct MdLayout {
+  uint64_t ctl, status, cws, hdr, keys0, keys1, idx0, idx1, perm, subs, sublen, subptr, segr, segb, segw, coord, bws,
+      total;
+  uint64_t cws_bytes, hdr_cap, sub_cap, coord_cap, bws_bytes, nseg, perm_stride;
+};
+
+static MdLayout md_layout(int nf, uint64_t n) {
+  MdLayout L;
+  uint64_t o = 0;
+  L.nseg = (n + kMdSeg - 1) / kMdSeg;
+  L.ctl = o; o = al256(o + 256);
+  L.status = o; o = al256(o + 64);
+  uint64_t n3[3] = {n, n, n};
+  uint32_t m3[3] = {kMdMode, kMdMode, kMdMode};
+  L.cws_bytes = compress_layout(3, n3, m3).total;
+  L.cws = o; o = al256(o + L.cws_bytes);
+  L.hdr_cap = compress_min_cap_impl(n, kMdMode);
+  L.hdr = o; o = al256(o + 3 * L.hdr_cap);
+  L.keys0 = o; o = al256(o + 8 * n);
+  L.keys1 = o; o = al256(o + 8 * n);
+  L.idx0 = o; o = al256(o + 4 * n);
+  L.idx1 = o; o = al256(o + 4 * n);
+  L.perm_stride = al256(4 * n);
+  L.perm = o; o = al256(o + L.perm_stride * nf);
+  L.sub_cap = al256(compress_bound_impl(n, kMdMode));
+  L.subs = o; o = al256(o + L.sub_cap * nf);
+  L.sublen = o; o = al256(o + 8 * 6);
+  L.subptr = o; o = al256(o + 8 * 6);
+  L.segr = o; o = al256(o + 4 * L.nseg);
+  L.segb = o; o = al256(o + 4 * L.nseg);
+  L.segw = o; o = al256(o + 4 * L.nseg);
+  L.coord_cap = 104 + align8(4 * L.nseg) + 12 * n + 64 + 8 * L.nseg;
+  L.coord = o; o = al256(o + L.coord_cap);
+  std::vector<uint64_t> nn(nf, n);
+  std::vector<uint32_t> mm(nf, kMdMode);
+  L.bws_bytes = std::max(compress_layout(nf, nn.data(), mm.data()).total, decompress_layout(nf, nn.data()).total);
+  L.bws = o; o = al256(o + L.bws_bytes);
+  L.total = o;
+  return L;
+}
+
+static int md_compress_impl(int nf, const float *const *fields, uint64_t n, double eb_rel, int md_mode, void *d_out,
+                            uint64_t out_cap, uint64_t *d_out_len, uint32_t *d_perm, void *d_ws, uint64_t ws_bytes,
+                            hipStream_t s) {
+  if ((nf != 3 && nf != 6) || md_mode < 0 || md_mode > 2 || n == 0 || n >= SZNB_MAX_N || !d_out || !d_ws)
+    return SZNB_EINVAL;
+  if (!(eb_rel > 0.0) || !std::isfinite(eb_rel)) return SZNB_EINVAL;
+  for (int f = 0; f < nf; f++)
+    if (!fields[f] || (reinterpret_cast<uintptr_t>(fields[f]) & 15u)) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  MdLayout L = md_layout(nf, n);
+  if (ws_bytes < L.total) return SZNB_ENOSPC;
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  MdCtl *ctl = reinterpret_cast<MdCtl *>(ws + L.ctl);
+  int *dstatus = reinterpret_cast<int *>(ws + L.status);
+  if (hipMemsetAsync(ws + L.ctl, 0, 256 + 64, s) != hipSuccess) return SZNB_EDEVICE;
+  const uint32_t k_ign = md_mode == 1 ? kMdPrx : 0u;
+  const int grid = dv->cus * 8;
+  // the SZ-LV inputs: the fields themselves, or their reordered copies
+  std::vector<const float *> szf;
+  const FState *cst[3] = {nullptr, nullptr, nullptr};
+  if (md_mode == 0) {
+    for (int f = 0; f < nf; f++) szf.push_back(fields[f]);
+  } else {
+    // coordinate lattices exactly as the compressor computes them
+    uint64_t n3[3] = {n, n, n};
+    double e3[3] = {eb_rel, eb_rel, eb_rel};
+    uint32_t m3[3] = {kMdMode, kMdMode, kMdMode};
+    void *ho[3];
+    uint64_t hc[3];
+    for (int c = 0; c < 3; c++) { ho[c] = ws + L.hdr + c * L.hdr_cap; hc[c] = L.hdr_cap; }
+    rc = compress_impl(3, fields, n3, e3, m3, ho, hc, nullptr, false, ws + L.cws, L.cws_bytes, s, true);
+    if (rc) return rc;
+    CLayout CL = compress_layout(3, n3, m3);
+    for (int c = 0; c < 3; c++) cst[c] = reinterpret_cast<const FState *>(ws + L.cws + CL.states + kStateStride * c);
+    uint64_t *k0 = reinterpret_cast<uint64_t *>(ws + L.keys0), *k1 = reinterpret_cast<uint64_t *>(ws + L.keys1);
+    uint32_t *i0 = reinterpret_cast<uint32_t *>(ws + L.idx0), *i1 = reinterpret_cast<uint32_t *>(ws + L.idx1);
+    SZNB_LAUNCH("md_bits", md_bits, dim3(1), dim3(64), 0, s, cst[0], cst[1], cst[2], ctl, n);
+    // a coordinate that cannot be keyed stops here, before any reordering
+    uint32_t hc4[4];
+    if (hipMemcpyAsync(hc4, ctl, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return SZNB_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
+    if (hc4[3]) return (int)hc4[3];
+    SZNB_LAUNCH("md_keys", md_keys, dim3(grid), dim3(256), 0, s, fields[0], fields[1], fields[2], n, cst[0], cst[1],
+                cst[2], ctl, k0, i0);
+    SZNB_LAUNCH("md_sort", md_sort, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, i0, k1, i1, n, k_ign, ctl);
+    const int first = md_mode == 2 ? 3 : 0;
+    for (int f = first; f < nf; f++) {
+      float *pf = reinterpret_cast<float *>(ws + L.perm + L.perm_stride * f);
+      SZNB_LAUNCH("md_gather", md_gather, dim3(grid), dim3(256), 0, s, fields[f], pf, i0, n, ctl);
+      szf.push_back(pf);
+    }
+    if (md_mode == 2) {
+      uint32_t *sr = reinterpret_cast<uint32_t *>(ws + L.segr), *sbits = reinterpret_cast<uint32_t *>(ws + L.segb);
+      uint32_t *sw = reinterpret_cast<uint32_t *>(ws + L.segw);
+      uint8_t *cs = ws + L.coord;
+      SZNB_LAUNCH("cpc_count", cpc_count, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, n, ctl, sr, sbits);
+      SZNB_LAUNCH("cpc_offsets", cpc_offsets, dim3(1), dim3(64), 0, s, sbits, (uint32_t)L.nseg, n, ctl, cst[0], cst[1],
+                  cst[2], cs, sw);
+      SZNB_LAUNCH("cpc_pack", cpc_pack, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, n, ctl, sr, sbits, sw, cs);
+    }
+    if (d_perm && hipMemcpyAsync(d_perm, i0, 4 * n, hipMemcpyDeviceToDevice, s) != hipSuccess) return SZNB_EDEVICE;
+  }
+  if (md_mode == 0 && d_perm) {
+    // identity order
+    std::vector<uint32_t> id(n);
+    for (uint64_t i = 0; i < n; i++) id[i] = (uint32_t)i;
+    if (hipMemcpy(d_perm, id.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess) return SZNB_EDEVICE;
+  }
+  // SZ-LV streams of the (reordered) fields
+  const int nsz = (int)szf.size();
+  std::vector<const uint8_t *> subp;
+  if (md_mode == 2) subp.push_back(ws + L.coord);
+  uint64_t *sublen = reinterpret_cast<uint64_t *>(ws + L.sublen);
+  if (nsz) {
+    std::vector<uint64_t> nn(nsz, n), caps(nsz, L.sub_cap);
+    std::vector<double> ee(nsz, eb_rel);
+    std::vector<uint32_t> mm(nsz, kMdMode);
+    std::vector<void *> outs(nsz);
+    for (int i = 0; i < nsz; i++) outs[i] = ws + L.subs + (uint64_t)i * L.sub_cap;
+    rc = compress_impl(nsz, szf.data(), nn.data(), ee.data(), mm.data(), outs.data(), caps.data(),
+                       sublen + (md_mode == 2 ? 1 : 0), true, ws + L.bws, L.bws_bytes, s);
+    if (rc) return rc;
+    for (int i = 0; i < nsz; i++) subp.push_back(static_cast<const uint8_t *>(outs[i]));
+  }
+  const int nsub = (int)subp.size();
+  if (hipMemcpyAsync(ws + L.subptr, subp.data(), 8ull * nsub, hipMemcpyHostToDevice, s) != hipSuccess)
+    return SZNB_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
+  SZNB_LAUNCH("md_assemble", md_assemble, dim3(grid), dim3(256), 0, s, static_cast<uint8_t *>(d_out), out_cap,
+              d_out_len, reinterpret_cast<const uint8_t *const *>(ws + L.subptr), sublen, nsub, md_mode, nf, n, k_ign,
+              ctl, dstatus);
+  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
+  // statuses: every SZ stream, then the container (whose ENOSPC may only
+  // echo a failed sub-stream)
+  for (int i = 0; i < nsz; i++) {
+    int v = 0;
+    if (hipMemcpy(&v, ws + L.bws + al256(sizeof(GCtl)) + kStateStride * i, 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return SZNB_EDEVICE;
+    if (v) return v;
+  }
+  int st = 0;
+  if (hipMemcpy(&st, dstatus, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
+  return st;
+}
+
+static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_t n, float *const *outs, void *d_ws,
+                              uint64_t ws_bytes, hipStream_t s) {
+  if ((nf != 3 && nf != 6) || !d_in || in_len < 96 || n == 0 || n >= SZNB_MAX_N || !d_ws) return SZNB_EINVAL;
+  for (int f = 0; f < nf; f++)
+    if (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 15u)) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  MdLayout L = md_layout(nf, n);
+  if (ws_bytes < L.total) return SZNB_ENOSPC;
+  uint8_t h[96];
+  if (hipMemcpyAsync(h, d_in, 96, hipMemcpyDeviceToHost, s) != hipSuccess) return SZNB_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
+  uint32_t magic;
+  uint64_t hn, total, offs[6];
+  std::memcpy(&magic, h, 4);
+  const int md_mode = h[6], hnf = h[7];
+  std::memcpy(&hn, h + 8, 8);
+  std::memcpy(&total, h + 24, 8);
+  std::memcpy(offs, h + 32, 48);
+  if (magic != 0x444D5A53u || h[4] != 1 || md_mode > 2 || hnf != nf || hn != n || total > in_len) return SZNB_ECORRUPT;
+  const int nsub = md_mode == 2 ? nf - 2 : nf;
+  uint64_t ends[6];
+  for (int i = 0; i < nsub; i++) {
+    ends[i] = i + 1 < nsub ? offs[i + 1] : total;
+    if (offs[i] < 96 || ends[i] < offs[i] || ends[i] > total || (offs[i] & 7u)) return SZNB_ECORRUPT;
+  }
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  const uint8_t *in = static_cast<const uint8_t *>(d_in);
+  int *dstatus = reinterpret_cast<int *>(ws + L.status);
+  if (hipMemsetAsync(dstatus, 0, 4, s) != hipSuccess) return SZNB_EDEVICE;
+  int first = 0;
+  if (md_mode == 2) {
+    SZNB_LAUNCH("cpc_decode", cpc_decode, dim3((unsigned)((L.nseg + 63) / 64)), dim3(64), 0, s, in + offs[0],
+                ends[0] - offs[0], n, outs[0], outs[1], outs[2], dstatus);
+    first = 1;
+  }
+  const int nsz = nsub - first;
+  if (nsz) {
+    std::vector<const void *> st(nsz);
+    std::vector<uint64_t> ln(nsz), nn(nsz, n);
+    std::vector<float *> oo(nsz);
+    for (int i = 0; i < nsz; i++) {
+      st[i] = in + offs[first + i];
+      ln[i] = ends[first + i] - offs[first + i];
+      oo[i] = outs[md_mode == 2 ? 3 + i : i];
+    }
+    rc = decompress_impl(nsz, st.data(), ln.data(), oo.data(), nn.data(), ws + L.bws, L.bws_bytes, s);
+    if (rc) return rc;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
+  int stv = 0;
+  if (hipMemcpy(&stv, dstatus, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
+  if (stv) return stv;
+  for (int i = 0; i < nsz; i++) {
+    int v = 0;
+    if (hipMemcpy(&v, ws + L.bws + al256(sizeof(GCtl)) + kStateStride * i, 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return SZNB_EDEVICE;
+    if (v) return v;
+  }
+  return SZNB_OK;
+}
+
 }  // namespace sznb
 
 using namespace sznb;
@@ -477,6 +711,24 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
     if (v != SZNB_OK && first == SZNB_OK) first = v;
   }
   return first;
+}
+
+uint64_t sznb_md_workspace_bytes(int nf, uint64_t n) { return md_layout(nf, n).total; }
+
+uint64_t sznb_md_bound(int nf, uint64_t n) {
+  return 96 + (uint64_t)nf * align8(compress_bound_impl(n, kMdMode)) + align8(md_layout(nf, n).coord_cap);
+}
+
+int sznb_md_compress(int nf, const float *const *h_fields, uint64_t n, double eb_rel, int md_mode, void *d_out,
+                     uint64_t out_cap, uint64_t *d_out_len, uint32_t *d_perm_or_null, void *d_ws, uint64_t ws_bytes,
+                     hipStream_t stream) {
+  return md_compress_impl(nf, h_fields, n, eb_rel, md_mode, d_out, out_cap, d_out_len, d_perm_or_null, d_ws, ws_bytes,
+                          stream);
+}
+
+int sznb_md_decompress(const void *d_in, uint64_t in_len, int nf, uint64_t n, float *const *h_outs, void *d_ws,
+                       uint64_t ws_bytes, hipStream_t stream) {
+  return md_decompress_impl(d_in, in_len, nf, n, h_outs, d_ws, ws_bytes, stream);
 }
 
 int sznb_profile(int enable) {

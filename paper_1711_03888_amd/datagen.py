@@ -67,8 +67,11 @@ def cosmology(n: int = 1 << 26, seed: int = 2, n_halos: int | None = None,
 
 
 def md_lattice(cells=(64, 64, 128), a: float = 3.6, sigma: float = 0.05,
-               seed: int = 3, shuffle_frac: float = 0.05, blk: int = 256) -> dict[str, np.ndarray]:
-    """FCC lattice in lattice-index order with thermal noise (AMDF stand-in)."""
+               seed: int = 3, shuffle_frac: float = 0.05, blk: int = 256,
+               velocities: bool = False) -> dict[str, np.ndarray]:
+    """FCC lattice in lattice-index order with thermal noise (AMDF stand-in).
+    With velocities, also Maxwell-Boltzmann velocity components N(0, 1) per
+    atom, drawn from their own generator (the coordinates do not change)."""
     rng = np.random.default_rng(seed)
     ci, cj, ck = cells
     basis = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
@@ -83,7 +86,11 @@ def md_lattice(cells=(64, 64, 128), a: float = 3.6, sigma: float = 0.05,
     for c in np.sort(chosen):
         perm[c * blk:(c + 1) * blk] = c * blk + rng.permutation(blk)
     pos = pos[perm]
-    return {name: pos[:, d].astype(np.float32) for d, name in enumerate(FIELD_NAMES[:3])}
+    out = {name: pos[:, d].astype(np.float32) for d, name in enumerate(FIELD_NAMES[:3])}
+    if velocities:
+        vel = np.random.default_rng(seed + 1000).normal(0.0, 1.0, size=(n, 3))[perm]
+        out.update({name: vel[:, d].astype(np.float32) for d, name in enumerate(FIELD_NAMES[3:])})
+    return out
 
 
 def batch_spec(n_fields: int = 512, seed: int = 4, lo: float = 16.0, hi: float = 24.0):

@@ -60,6 +60,13 @@ def lib():
         L.sznb_profile.argtypes = [ctypes.c_int]
         L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
         L.sznb_strerror.argtypes = [ctypes.c_int]
+        L.sznb_md_workspace_bytes.argtypes = [ctypes.c_int, _u64]
+        L.sznb_md_workspace_bytes.restype = _u64
+        L.sznb_md_bound.argtypes = [ctypes.c_int, _u64]
+        L.sznb_md_bound.restype = _u64
+        L.sznb_md_compress.argtypes = [ctypes.c_int, _vp, _u64, ctypes.c_double, ctypes.c_int, _vp, _u64, _vp, _vp,
+                                       _vp, _u64, _vp]
+        L.sznb_md_decompress.argtypes = [_vp, _u64, ctypes.c_int, _u64, _vp, _vp, _u64, _vp]
         L.sznb_strerror.restype = ctypes.c_char_p
         _lib = L
     return _lib
@@ -225,3 +232,55 @@ def profile_summary(max_kernels: int = 64):
         nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
         out[nm] = (tot[i], cnt[i])
     return out
+
+
+# ------------------------------------------------ molecular-dynamics modes
+
+MD_SPEED, MD_TRADEOFF, MD_COMPRESSION = 0, 1, 2
+
+
+def md_workspace_bytes(nf: int, n: int) -> int:
+    return int(lib().sznb_md_workspace_bytes(nf, n))
+
+
+def md_bound(nf: int, n: int) -> int:
+    return int(lib().sznb_md_bound(nf, n))
+
+
+def md_compress(fields: Sequence[torch.Tensor], eb_rel: float, md_mode: int, *, ws=None, out=None,
+                want_perm: bool = False, stream=None):
+    """Container of an MD snapshot (x, y, z[, vx, vy, vz]); returns (bytes
+    tensor, permutation or None).  Waits for the stream."""
+    fields = [_field(f) for f in fields]
+    nf, n = len(fields), fields[0].numel()
+    if any(f.numel() != n for f in fields):
+        raise ValueError("fields must have equal length")
+    dev = fields[0].device
+    wsb = md_workspace_bytes(nf, n)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, dev)
+    if out is None:
+        out = torch.empty(md_bound(nf, n), dtype=torch.uint8, device=dev)
+    olen = torch.zeros(1, dtype=torch.int64, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev) if want_perm else None
+    rc = lib().sznb_md_compress(nf, _arr(_vp, [f.data_ptr() for f in fields]), n, float(eb_rel), int(md_mode),
+                                out.data_ptr(), out.numel(), olen.data_ptr(),
+                                perm.data_ptr() if perm is not None else None, ws.data_ptr(), ws.numel(),
+                                _stream(stream))
+    _check(rc, "md_compress")
+    return out[:int(olen.item())], perm
+
+
+def md_decompress(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, stream=None):
+    if blob.dtype != torch.uint8 or not blob.is_cuda or not blob.is_contiguous():
+        raise ValueError("container must be a contiguous uint8 CUDA tensor")
+    dev = blob.device
+    wsb = md_workspace_bytes(nf, n)
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, dev)
+    if outs is None:
+        outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(nf)]
+    rc = lib().sznb_md_decompress(blob.data_ptr(), blob.numel(), nf, n, _arr(_vp, [o.data_ptr() for o in outs]),
+                                  ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "md_decompress")
+    return outs

@@ -1,0 +1,163 @@
+"""Pins of the MD-mode oracle (R-index, partial radix sort, CPC2000 key code).
+
+Each pin checks the oracle against something other than itself: bit strings
+built character by character for the R-index, a literal 3-bit-digit LSD radix
+sort for PRX (Sec. 5.2), brute-force Rice parameter search, a hand-worked
+Rice example, lossless key round trips and the error bound of every mode.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import md
+from paper_1711_03888_amd import datagen
+
+
+def _small_md(cells=(8, 8, 16), seed=3, velocities=False):
+    return datagen.md_lattice(cells=cells, seed=seed, velocities=velocities)
+
+
+def test_rindex_matches_bit_strings():
+    # key = for each bit j from the top: x_j y_j z_j, read as one binary number
+    snap = _small_md()
+    coords = [snap["xx"], snap["yy"], snap["zz"]]
+    key, B = md.rindex_keys(coords, 1e-3)
+    ps = [oracle.lattice(c, 1e-3) for c in coords]
+    for i in range(0, key.size, 97):
+        s = "".join(format(int(ps[0][i]), "0%db" % B)[j] + format(int(ps[1][i]), "0%db" % B)[j]
+                    + format(int(ps[2][i]), "0%db" % B)[j] for j in range(B))
+        assert int(s, 2) == int(key[i])
+
+
+def test_rindex_bits_per_coordinate():
+    snap = _small_md()
+    coords = [snap["xx"], snap["yy"], snap["zz"]]
+    _, B = md.rindex_keys(coords, 1e-3)
+    top = max(int(oracle.params(c, 1e-3)["P"]) for c in coords)
+    assert 2 ** (B - 1) <= top < 2 ** B
+
+
+def test_deinterleave_inverts_rindex():
+    snap = _small_md()
+    coords = [snap["xx"], snap["yy"], snap["zz"]]
+    key, B = md.rindex_keys(coords, 1e-4)
+    back = md.deinterleave(key, B)
+    for c in range(3):
+        assert np.array_equal(back[c], oracle.lattice(coords[c], 1e-4).astype(np.int64))
+
+
+def _lsd_radix_3bit(keys, k, ndigits):
+    """The paper's partial radix sort written out: buckets on 3-bit digits
+    from digit k upward, each pass stable."""
+    order = list(range(len(keys)))
+    for d in range(k, ndigits):
+        buckets = [[] for _ in range(8)]
+        for i in order:
+            buckets[(int(keys[i]) >> (3 * d)) & 7].append(i)
+        order = [i for b in buckets for i in b]
+    return order
+
+
+@pytest.mark.parametrize("k", [0, 2, 6])
+def test_prx_is_lsd_radix_from_digit_k(k):
+    rng = np.random.default_rng(7)
+    n = md.SEG + 3001  # two segments, the second ragged
+    keys = rng.integers(0, 1 << 30, size=n).astype(np.uint64)
+    keys[:500] = keys[:500] & np.uint64(0x3f)  # many ties below digit 2
+    perm = md.segment_order(keys, k)
+    for s in range(0, n, md.SEG):
+        seg = keys[s:s + md.SEG]
+        want = [s + i for i in _lsd_radix_3bit(seg, k, 10)]
+        assert perm[s:s + md.SEG].tolist() == want
+
+
+def test_prx_order_properties():
+    snap = _small_md(cells=(16, 16, 32))
+    coords = [snap["xx"], snap["yy"], snap["zz"]]
+    key, _ = md.rindex_keys(coords, 1e-4)
+    for k in (0, 6):
+        perm = md.segment_order(key, k)
+        assert np.array_equal(np.sort(perm), np.arange(key.size))  # a bijection
+        for s in range(0, key.size, md.SEG):
+            seg = perm[s:s + md.SEG]
+            assert seg.min() == s and seg.max() < s + md.SEG  # stays in its segment
+            top = key[seg] >> np.uint64(3 * k)
+            assert np.all(np.diff(top.astype(np.int64)) >= 0)
+
+
+def test_rice_parameter_brute_force():
+    rng = np.random.default_rng(9)
+    for scale in (1, 40, 5000, 1 << 20):
+        d = rng.geometric(1.0 / scale, size=300).astype(np.uint64) - np.uint64(1)
+        kb = 39
+        costs = []
+        for r in range(kb + 1):
+            c = 0
+            for v in d.tolist():
+                q = v >> r
+                c += 32 + kb if q >= 32 else q + 1 + r
+            costs.append(c)
+        assert md.rice_parameter(d, kb) == costs.index(min(costs))
+
+
+def test_cpc_hand_example():
+    # keys 5 6 8 8 13 in 6-bit keys: deltas 1 2 0 5; Rice costs r=0: 12,
+    # r=1: 11, r=2: 13 -> r = 1.  Bits: 000101 | 000001 | 0 1 | 10 0 | 0 0 | 110 1
+    words, nbits = md.cpc_encode_segment(np.array([5, 6, 8, 8, 13], np.uint64), 6)
+    bits = "000101" + "000001" + "01" + "100" + "00" + "1101"
+    assert nbits == len(bits) == 23
+    assert words.tolist() == [int(bits + "0" * 9, 2)]
+    back = md.cpc_decode_segment(words, 5, 6)
+    assert back.tolist() == [5, 6, 8, 8, 13]
+
+
+def test_cpc_escape_round_trip():
+    keys = np.array([0, 1, 2, 3, 1 << 40, (1 << 40) + 1, (1 << 44) - 1], np.uint64)
+    words, nbits = md.cpc_encode_segment(keys, 45)
+    r = md.rice_parameter(np.diff(keys), 45)
+    assert r == 0
+    # first key + parameter + three 1-deltas + escape + 1-delta + escape
+    assert nbits == 45 + 6 + 3 * 2 + (32 + 45) + 2 + (32 + 45)
+    assert md.cpc_decode_segment(words, keys.size, 45).tolist() == keys.tolist()
+
+
+@pytest.mark.parametrize("mode", [md.SPEED, md.TRADEOFF, md.COMPRESSION])
+@pytest.mark.parametrize("velocities", [False, True])
+def test_md_modes_error_bound_and_order(mode, velocities):
+    snap = _small_md(cells=(16, 16, 20), velocities=velocities)
+    names = list(snap)
+    fields = [snap[k] for k in names]
+    n = fields[0].size
+    eb = 1e-4
+    blob, perm = md.compress_md(fields, eb, mode)
+    out = md.decompress_md(blob)
+    assert len(out) == len(fields)
+    if mode == md.SPEED:
+        assert np.array_equal(perm, np.arange(n))
+    for f, y in zip(fields, out):
+        eb_abs = oracle.params(f, eb)["eb_abs"]
+        assert np.abs(f[perm].astype(np.float64) - y.astype(np.float64)).max() <= eb_abs
+
+
+def test_cpc_coordinates_are_lattice_points():
+    snap = _small_md(cells=(16, 16, 20))
+    fields = [snap["xx"], snap["yy"], snap["zz"]]
+    blob, perm = md.compress_md(fields, 1e-4, md.COMPRESSION)
+    out = md.decompress_md(blob)
+    for c in range(3):
+        pr = oracle.params(fields[c], 1e-4)
+        p = oracle.lattice(fields[c][perm], 1e-4)
+        assert np.array_equal(out[c].view(np.uint32),
+                              oracle.reconstruct_array(p, pr["step"], pr["mn"]).view(np.uint32))
+
+
+def test_container_layout():
+    import struct
+    snap = _small_md(cells=(8, 8, 8), velocities=True)
+    fields = list(snap.values())
+    blob, _ = md.compress_md(fields, 1e-3, md.COMPRESSION)
+    magic, ver, mode, nf, n, seg, k, total, *offs = struct.unpack_from("<4sHBBQIIQ6Q", blob, 0)
+    assert (magic, ver, mode, nf, n, seg, k, total) == (b"SZMD", 1, 2, 6, fields[0].size, md.SEG, 0, len(blob))
+    assert offs[0] == md.MD_HDR and all(o % 8 == 0 for o in offs[:4]) and offs[4:] == [0, 0]
+    assert blob[offs[0]:offs[0] + 4] == b"SZCP"
+    assert all(blob[o:o + 4] == b"SZNB" for o in offs[1:4])
