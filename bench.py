@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "compress+decompress GB/s and ratio at eb=1e-4·range vs oracle; % HBM peak"
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def algorithmic_bytes(kernel, n_total, comp_bytes):
@@ -40,6 +41,52 @@ def algorithmic_bytes(kernel, n_total, comp_bytes):
     }.get(kernel)
 
 
+def measured_traffic(kernel, tag):
+    """HBM bytes per launch of `kernel` from the committed counter passes of
+    this workload, or None when they were taken on other library sources."""
+    path = os.path.join(PROFILES, "traffic_%s.json" % tag)
+    if not os.path.exists(path):
+        return None
+    from paper_1711_03888_amd.profile_summary import source_hash
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != source_hash() or kernel not in t.get("kernels", {}):
+        return None
+    return round(t["kernels"][kernel]["bytes"])
+
+
+def md_modes(dev, eb, reps):
+    """The three MD modes on the 2M-atom FCC snapshot: GB/s and ratio."""
+    import torch
+
+    from paper_1711_03888_amd import datagen, sznb
+    snap = datagen.md_lattice()
+    fields = [torch.from_numpy(v).to(dev) for v in snap.values()]
+    n = fields[0].numel()
+    ws = sznb.workspace(sznb.md_workspace_bytes(3, n), dev)
+    out = torch.empty(sznb.md_bound(3, n), dtype=torch.uint8, device=dev)
+    outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)]
+    res = {}
+    for mode, name in ((0, "best_speed"), (1, "best_tradeoff"), (2, "best_compression")):
+        blob, _ = sznb.md_compress(fields, eb, mode, ws=ws, out=out)
+        sznb.md_decompress(blob, 3, n, ws=ws, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            blob, _ = sznb.md_compress(fields, eb, mode, ws=ws, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            sznb.md_decompress(blob, 3, n, ws=ws, outs=outs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res[name] = {"ratio": round(12.0 * n / blob.numel(), 4),
+                     "compress_GBps": round(12.0 * n * reps / (t1 - t0) / 1e9, 2),
+                     "decompress_GBps": round(12.0 * n * reps / (t2 - t1) / 1e9, 2)}
+    res["workload"] = "FCC lattice %d atoms x 3 float32 coordinates, eb_rel %g" % (n, eb)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,8 +96,9 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-4)
     ap.add_argument("--block-log2", type=int, default=12)
     ap.add_argument("--policy", default="bestfit", choices=["lv", "lcf", "bestfit"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 19, help="values per field timed on the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="values per field timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-md", action="store_true", help="skip the MD-mode measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
@@ -133,8 +181,10 @@ def main():
     dom = max((k for k in kern if algorithmic_bytes(k, n_total, comp_bytes)), key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
     ach = algorithmic_bytes(dom, n_total, comp_bytes) / (avg_ms * 1e-3) / 1e9
+    tag = "cosmology_%d_%s_eb%g_S%d" % (n, args.policy, args.eb, 1 << args.block_log2)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4)}
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(dom, tag),
+            "algorithmic_bytes": algorithmic_bytes(dom, n_total, comp_bytes), "avg_launch_ms": round(avg_ms, 4)}
 
     out = {
         "metric": METRIC,
@@ -162,6 +212,9 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(kern.items())},
     }
+
+    if not args.no_md:
+        out["md_modes"] = md_modes(dev, args.eb, 5)
 
     if not args.no_cpu_baseline:
         import oracle
