@@ -111,6 +111,63 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
 
 const char *sznb_strerror(int status);
 
+/* ---- learned predictor selector (SZNB_PRED_LEARNED)
+ * Not part of the paper, whose methods fix one predictor each (Sec. 5.1): a
+ * small network 16 -> 32 -> 32 -> 3 (ReLU) reads 16 statistics of a block's
+ * lattice values and picks LV, LCF or QCF; when the margin between its two
+ * largest logits is below tau (or not a number) the block falls back to the
+ * exhaustive trial of SZNB_PRED_BESTFIT.  The predictor ids are stored in the
+ * stream, so decompression never needs the network.
+ * Parameters, 1699 float32 in this order: W1[32][16], b1[32], W2[32][32],
+ * b2[32], W3[3][32], b3[3].  Inference rounds features and weights to
+ * bfloat16 (nearest, ties to even), keeps biases in float32, accumulates each
+ * neuron from its bias with one fused multiply-add per input in ascending
+ * order, and rounds hidden outputs (after ReLU) to bfloat16.
+ * Features of a block of lattice values p (length len, span P' = max(P,1)),
+ * Dp / D2p its LV / LCF residuals, F(v) = bit length of v + (8 bits after the
+ * leading one)/256, every ratio one fp64 division rounded to float32:
+ *   0 sum p/(len P')  1 (max p - min p)/P'  2 F(sum|Dp|)-F(len)
+ *   3 F(sum|D2p|)-F(len)  4 F(max|Dp|)  5 F(max|D2p|)  6 #(Dp=0)/len
+ *   7 #(D2p=0)/len  8 #(|Dp|<=1)/len  9 #(|D2p|<=1)/len
+ *   10 #(sign changes of Dp)/len  11 F(sum bitlen|Dp|)-F(len)
+ *   12 F(sum bitlen|D2p|)-F(len)  13 #(|Dp|>=32768)/len  14 F(P')  15 1 */
+#define SZNB_MLP_PARAMS 1699u
+#define SZNB_FEATURES 16u
+
+/* Load the selector used by SZNB_PRED_LEARNED on the current device (host
+ * parameters, copied; weights rounded to bfloat16 here).  Until it is
+ * called, compressing with SZNB_PRED_LEARNED returns SZNB_EINVAL. */
+int sznb_set_selector(const float *h_params, float tau);
+
+/* Training data: for every block of every field (blocks in field order),
+ * the 16 features (d_feat, float32 [blocks][16]), the three trial costs
+ * (d_cost, u64 [blocks][3], 2^-16 bit units) and the trial's choice
+ * (d_label, u8 [blocks]).  All fields must share one block size.  Returns
+ * after enqueueing; constant or failed fields give zero rows. */
+uint64_t sznb_features_workspace_bytes(int nf, const uint64_t *h_n, const uint32_t *h_mode);
+int sznb_block_features(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                        const uint32_t *h_mode, float *d_feat, uint64_t *d_cost, uint8_t *d_label,
+                        void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+
+/* Blocks of each field of the last compression in d_ws that the learned
+ * policy handed to the exhaustive trial (waits for the stream). */
+int sznb_compress_fallbacks(const void *d_ws, int nf, uint32_t *h_out, hipStream_t stream);
+
+/* Training (float32, deterministic): gradient of the mean softmax
+ * cross-entropy over a batch of feature rows and labels (d_grad: 1699
+ * floats, d_loss: 1 float), and one Adam step (Kingma and Ba, 2015) with
+ * bias correction; step counts from 1. */
+uint64_t sznb_mlp_grad_workspace_bytes(uint32_t batch);
+int sznb_mlp_grad(const float *d_params, const float *d_feat, const uint8_t *d_label, uint32_t batch,
+                  float *d_grad, float *d_loss, void *d_ws, uint64_t ws_bytes, hipStream_t stream);
+int sznb_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, uint32_t step, float lr,
+                  float beta1, float beta2, float eps, hipStream_t stream);
+
+/* The compressor's bfloat16 inference on nb feature rows: logits [nb][3],
+ * choice (argmax, ties to the lowest) and margin to the runner-up. */
+int sznb_mlp_infer(const float *d_params, const float *d_feat, uint64_t nb, float *d_logits,
+                   uint8_t *d_choice, float *d_margin, hipStream_t stream);
+
 /* ---- molecular-dynamics snapshots: the paper's three modes (Sec. 5.2, Sec. 6)
  * md_mode 0 best_speed:       SZ-LV on every field in stored order;
  * md_mode 1 best_tradeoff:    particles reordered by a stable sort of their

@@ -59,6 +59,15 @@ def lib():
         L.sznbref_canonical.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.sznbref_reconstruct.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_float]
         L.sznbref_reconstruct.restype = ctypes.c_float
+        L.sznbref_features.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
+                                       ctypes.c_void_p]
+        L.sznbref_mlp_logits.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+        L.sznbref_bf16.argtypes = [ctypes.c_float]
+        L.sznbref_bf16.restype = ctypes.c_float
+        L.sznbref_select_learned.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
+                                             ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
+        L.sznbref_compress_learned.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint32,
+                                               ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]
         L.sznbref_reconstruct_array.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_double, ctypes.c_float,
                                                 ctypes.c_void_p]
         _lib = L
@@ -75,12 +84,18 @@ def _f32(x) -> np.ndarray:
     return np.ascontiguousarray(x, dtype=np.float32)
 
 
-def compress(x, eb: float, mode: int = LV | EB_REL, pred=None) -> bytes:
+def compress(x, eb: float, mode: int = LV | EB_REL, pred=None, selector=None) -> bytes:
+    """selector = (1699 float32 parameters, tau) for the learned policy."""
     x = _f32(x)
     L = lib()
     out = ctypes.POINTER(ctypes.c_uint8)()
     n = ctypes.c_size_t(0)
-    if pred is None:
+    if selector is not None:
+        w = np.ascontiguousarray(selector[0], dtype=np.float32)
+        assert w.size == MLP_NPARAM
+        st = L.sznbref_compress_learned(x.ctypes.data, x.size, eb, mode, w.ctypes.data, float(selector[1]),
+                                        ctypes.byref(out), ctypes.byref(n))
+    elif pred is None:
         st = L.sznbref_compress(x.ctypes.data, x.size, eb, mode, ctypes.byref(out), ctypes.byref(n))
     else:
         pred = np.ascontiguousarray(pred, dtype=np.uint8)
@@ -91,6 +106,44 @@ def compress(x, eb: float, mode: int = LV | EB_REL, pred=None) -> bytes:
     data = ctypes.string_at(out, n.value)
     L.sznbref_free(out)
     return data
+
+
+MLP_NPARAM = 1699
+N_FEATURES = 16
+
+
+def features(q, S: int, P: int) -> np.ndarray:
+    """Selector features of every block of a lattice array: float32 [nb, 16]."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    nb = -(-q.size // S)
+    out = np.zeros((nb, N_FEATURES), np.float32)
+    lib().sznbref_features(q.ctypes.data, q.size, S, int(P), out.ctypes.data)
+    return out
+
+
+def mlp_logits(w, feat) -> np.ndarray:
+    """Bit-faithful bfloat16 inference: float32 logits [nb, 3]."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    feat = np.ascontiguousarray(feat, dtype=np.float32).reshape(-1, N_FEATURES)
+    out = np.zeros((feat.shape[0], 3), np.float32)
+    lib().sznbref_mlp_logits(w.ctypes.data, feat.ctypes.data, feat.shape[0], out.ctypes.data)
+    return out
+
+
+def bf16(x: float) -> float:
+    return float(lib().sznbref_bf16(x))
+
+
+def select_learned(q, S: int, P: int, w, tau: float):
+    """(predictor per block, fallback flag per block) of the learned policy."""
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    nb = -(-q.size // S)
+    pred = np.zeros(nb, np.uint8)
+    fb = np.zeros(nb, np.uint8)
+    lib().sznbref_select_learned(q.ctypes.data, q.size, S, int(P), w.ctypes.data, float(tau),
+                                 pred.ctypes.data, fb.ctypes.data)
+    return pred, fb
 
 
 def decompress(stream: bytes) -> np.ndarray:

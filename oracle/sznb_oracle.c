@@ -728,6 +728,205 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
     return OK;
 }
 
+/* ---------------------------------------------------- learned selector */
+
+/* The learned policy replaces the exhaustive trial of select_pred by a small
+ * network that reads cheap statistics of the block.  Not in the paper (its
+ * methods fix one predictor each, Sec. 5.1); the definitions here are this
+ * compressor's own.
+ *
+ * Features of a block of lattice values p_0..p_{len-1} (exact integer sums
+ * and counts, so they do not depend on any summation order), with Dp_j and
+ * D2p_j the LV and LCF residuals of residual() and P' = max(P, 1):
+ *   0  sum p / (len P')            1  (max p - min p) / P'
+ *   2  F(sum |Dp|) - F(len)        3  F(sum |D2p|) - F(len)
+ *   4  F(max |Dp|)                 5  F(max |D2p|)
+ *   6  #(Dp = 0) / len             7  #(D2p = 0) / len
+ *   8  #(|Dp| <= 1) / len          9  #(|D2p| <= 1) / len
+ *   10 #(sign changes of Dp between neighbours) / len
+ *   11 F(sum bitlen |Dp|) - F(len) 12 F(sum bitlen |D2p|) - F(len)
+ *   13 #(|Dp| >= 32768) / len      14 F(P)        15 1
+ * F(v) = bit length of v plus the 8 bits after its leading one, over 256 (a
+ * fixed-point log2 that is exact in float32); every ratio is one fp64
+ * division rounded to float32. */
+static float flog(uint64_t v)
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) b++;
+    if (b == 0) return 0.0f;
+    uint64_t frac = b - 1 >= 8 ? (v >> (b - 9)) & 255u : (v << (9 - b)) & 255u;
+    return (float)b + (float)frac / 256.0f;
+}
+
+static float ratio_f(uint64_t a, uint64_t b) { return (float)((double)a / (double)b); }
+
+static uint32_t bitlen32(uint32_t v)
+{
+    uint32_t b = 0;
+    while (b < 32 && (v >> b) != 0) b++;
+    return b;
+}
+
+static void block_features(const int32_t *q, uint64_t len, int64_t P, float f[16])
+{
+    uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
+    int64_t sum_p = 0, mx = q[0], mn = q[0];
+    uint64_t s1 = 0, s2 = 0, m1 = 0, m2 = 0, z1 = 0, z2 = 0, o1 = 0, o2 = 0, sc = 0, b1 = 0, b2 = 0, esc = 0;
+    int32_t prev = 0;
+    for (uint64_t j = 0; j < len; j++) {
+        sum_p += q[j];
+        if (q[j] > mx) mx = q[j];
+        if (q[j] < mn) mn = q[j];
+        int32_t d1 = residual(q, j, 0), d2 = residual(q, j, 1);
+        uint32_t a1 = d1 < 0 ? (uint32_t)(-(int64_t)d1) : (uint32_t)d1;
+        uint32_t a2 = d2 < 0 ? (uint32_t)(-(int64_t)d2) : (uint32_t)d2;
+        s1 += a1; s2 += a2;
+        if (a1 > m1) m1 = a1;
+        if (a2 > m2) m2 = a2;
+        if (a1 == 0) z1++;
+        if (a2 == 0) z2++;
+        if (a1 <= 1) o1++;
+        if (a2 <= 1) o2++;
+        if (j >= 1 && ((d1 > 0 && prev < 0) || (d1 < 0 && prev > 0))) sc++;
+        b1 += bitlen32(a1);
+        b2 += bitlen32(a2);
+        if (a1 >= RADIUS) esc++;
+        prev = d1;
+    }
+    float fl = flog(len);
+    f[0] = ratio_f((uint64_t)sum_p, len * Pp);
+    f[1] = ratio_f((uint64_t)(mx - mn), Pp);
+    f[2] = flog(s1) - fl;
+    f[3] = flog(s2) - fl;
+    f[4] = flog(m1);
+    f[5] = flog(m2);
+    f[6] = ratio_f(z1, len);
+    f[7] = ratio_f(z2, len);
+    f[8] = ratio_f(o1, len);
+    f[9] = ratio_f(o2, len);
+    f[10] = ratio_f(sc, len);
+    f[11] = flog(b1) - fl;
+    f[12] = flog(b2) - fl;
+    f[13] = ratio_f(esc, len);
+    f[14] = flog(Pp);
+    f[15] = 1.0f;
+}
+
+/* bfloat16 rounding, round to nearest, ties to even (finite inputs) */
+static float bf16_round(float x)
+{
+    uint32_t u = f2u(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return u2f(u & 0xffff0000u);
+}
+
+/* Network 16 -> 32 -> 32 -> 3, ReLU.  Parameters in this order: W1[32][16],
+ * b1[32], W2[32][32], b2[32], W3[3][32], b3[3] (1699 floats).  Inference:
+ * inputs and weights rounded to bfloat16, biases kept in float32; each
+ * neuron starts from its bias and adds w_k x_k for k ascending with one
+ * fused multiply-add each; hidden outputs are ReLU then bfloat16-rounded. */
+#define MLP_NPARAM 1699
+static void mlp_logits(const float *w, const float feat[16], float z[3])
+{
+    const float *W1 = w, *B1 = w + 512, *W2 = w + 544, *B2 = w + 1568, *W3 = w + 1600, *B3 = w + 1696;
+    float x[16], h1[32], h2[32];
+    for (int k = 0; k < 16; k++) x[k] = bf16_round(feat[k]);
+    for (int j = 0; j < 32; j++) {
+        float acc = B1[j];
+        for (int k = 0; k < 16; k++) acc = fmaf(bf16_round(W1[16 * j + k]), x[k], acc);
+        h1[j] = bf16_round(acc > 0.0f ? acc : 0.0f);
+    }
+    for (int j = 0; j < 32; j++) {
+        float acc = B2[j];
+        for (int k = 0; k < 32; k++) acc = fmaf(bf16_round(W2[32 * j + k]), h1[k], acc);
+        h2[j] = bf16_round(acc > 0.0f ? acc : 0.0f);
+    }
+    for (int j = 0; j < 3; j++) {
+        float acc = B3[j];
+        for (int k = 0; k < 32; k++) acc = fmaf(bf16_round(W3[32 * j + k]), h2[k], acc);
+        z[j] = acc;
+    }
+}
+
+/* argmax of the logits (ties to the lowest index) unless the margin to the
+ * runner-up is below tau (or not a number): then the exhaustive trial. */
+static int select_learned(const int32_t *q, uint64_t len, int64_t P, const float *w, float tau, int *fallback)
+{
+    float f[16], z[3];
+    block_features(q, len, P, f);
+    mlp_logits(w, f, z);
+    int top = 0;
+    for (int k = 1; k < 3; k++)
+        if (z[k] > z[top]) top = k;
+    float second = -INFINITY;
+    for (int k = 0; k < 3; k++)
+        if (k != top && z[k] > second) second = z[k];
+    float margin = z[top] - second;
+    if (!(margin >= tau)) {
+        uint64_t c[3];
+        *fallback = 1;
+        return select_pred(q, len, c);
+    }
+    *fallback = 0;
+    return top;
+}
+
+int sznbref_features(const int32_t *q, uint64_t n, uint32_t S, int64_t P, float *feat)
+{
+    for (uint64_t b = 0; b * S < n; b++) {
+        uint64_t len = (b + 1) * S <= n ? S : n - b * S;
+        block_features(q + b * S, len, P, feat + 16 * b);
+    }
+    return OK;
+}
+
+int sznbref_mlp_logits(const float *w, const float *feat, uint64_t nb, float *z)
+{
+    for (uint64_t b = 0; b < nb; b++) mlp_logits(w, feat + 16 * b, z + 3 * b);
+    return OK;
+}
+
+float sznbref_bf16(float x) { return bf16_round(x); }
+
+int sznbref_select_learned(const int32_t *q, uint64_t n, uint32_t S, int64_t P, const float *w, float tau,
+                           uint8_t *pred, uint8_t *fallback)
+{
+    make_log_table();
+    for (uint64_t b = 0; b * S < n; b++) {
+        uint64_t len = (b + 1) * S <= n ? S : n - b * S;
+        int fb;
+        pred[b] = (uint8_t)select_learned(q + b * S, len, P, w, tau, &fb);
+        fallback[b] = (uint8_t)fb;
+    }
+    return OK;
+}
+
+/* learned policy end to end: range, lattice, per-block learned choice, then
+ * the same stream as every other policy */
+int sznbref_compress_learned(const float *x, uint64_t n, double eb, uint32_t mode, const float *w, float tau,
+                             uint8_t **out, size_t *out_len)
+{
+    if ((mode & 3u) != 3u) return E_INVAL;
+    int bl = block_log2_of(mode);
+    if (bl < 10 || bl > 14) return E_INVAL;
+    if (n >= (1ull << 31)) return E_INVAL;
+    params_t p;
+    int st = range_and_bound(x, n, eb, (mode >> 4) & 1u, &p);
+    if (st) return st;
+    uint64_t S = 1ull << bl, nb = (n + S - 1) / S;
+    uint8_t *pred = calloc(nb ? nb : 1, 1), *fb = calloc(nb ? nb : 1, 1);
+    if (!p.is_const) {
+        int32_t *q = malloc(sizeof(int32_t) * n);
+        for (uint64_t i = 0; i < n; i++) q[i] = lattice(x[i], &p);
+        sznbref_select_learned(q, n, (uint32_t)S, p.P, w, tau, pred, fb);
+        free(q);
+    }
+    st = sznbref_compress_blocks(x, n, eb, mode, pred, out, out_len);
+    free(pred);
+    free(fb);
+    return st;
+}
+
 void sznbref_free(void *p) { free(p); }
 
 /* ------------------------------------------- introspection for the tests */

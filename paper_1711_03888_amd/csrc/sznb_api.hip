@@ -1,5 +1,6 @@
 // Host side of the sznb C ABI: argument checks, workspace layout, launches.
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -25,6 +26,14 @@ __global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int);
 __global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *);
 
+template <int E>
+__global__ void k_features(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, float *, uint64_t *,
+                           uint8_t *);
+__global__ void mlp_fwd_bwd(const float *, const float *, const uint8_t *, uint32_t, float *);
+__global__ void mlp_grad(const float *, const float *, uint32_t, float *);
+__global__ void mlp_loss(const float *, uint32_t, float *);
+__global__ void mlp_adam(float *, float *, float *, const float *, uint32_t, float, float, float, float);
+__global__ void mlp_infer(const float *, const float *, uint64_t, float *, uint8_t *, float *);
 struct MdCtl;
 __global__ void md_bits(const FState *, const FState *, const FState *, MdCtl *, uint64_t);
 __global__ void md_keys(const float *, const float *, const float *, uint64_t, const FState *, const FState *,
@@ -92,6 +101,8 @@ struct DevInfo {
   int ok = 0;
   int cus = 0;
   size_t lds_per_block = 0;
+  float *sel = nullptr;   // learned selector parameters on this device
+  float tau = 0.0f;
 };
 static DevInfo g_dev[64];
 static std::mutex g_mu;
@@ -289,6 +300,11 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
     c.enc = reinterpret_cast<uint32_t *>(ws + L.enc[f]);
     c.book = reinterpret_cast<uint32_t *>(ws + L.book[f]);
     c.lbflag = reinterpret_cast<uint64_t *>(ws + L.lbflag) + L.gblock0[f];
+    if (c.policy == 3) {
+      if (!dv->sel) return SZNB_EINVAL;  // no selector loaded on this device
+      c.sel = dv->sel;
+      c.tau = dv->tau;
+    }
     fb0[f] = L.gblock0[f];
   }
   fb0[nf] = L.total_blocks;
@@ -306,6 +322,85 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
   P.ws = ws;
   P.L = L;
   return compress_run(P, stream, dv, params_only);
+}
+
+template <int E>
+static int launch_features(const Launch &P, hipStream_t s, int grid, float *feat, uint64_t *cost, uint8_t *label) {
+  const CField *F = reinterpret_cast<const CField *>(P.ws + P.L.fields);
+  const uint64_t *fb0 = reinterpret_cast<const uint64_t *>(P.ws + P.L.fb0);
+  uint32_t *logt = nullptr;
+  if (hipGetSymbolAddress(reinterpret_cast<void **>(&logt), HIP_SYMBOL(g_logt)) != hipSuccess) return SZNB_EDEVICE;
+  SZNB_LAUNCH("k_features", k_features<E>, dim3(grid), dim3(kThreads), 0, s, F, P.nf, fb0, P.total_blocks, logt, feat,
+              cost, label);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+// features, trial costs and trial choice of every block of a field table
+static int features_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
+                         const uint32_t *mode, float *feat, uint64_t *cost, uint8_t *label, void *d_ws,
+                         uint64_t ws_bytes, hipStream_t stream) {
+  if (nf <= 0 || !feat || !cost || !label) return SZNB_EINVAL;
+  // stream headers of the parameter pass go to the end of the workspace
+  std::vector<uint64_t> caps(nf);
+  std::vector<void *> outs(nf);
+  CLayout L = compress_layout(nf, n, mode);
+  uint64_t o = L.total;
+  for (int f = 0; f < nf; f++) {
+    if (!mode_ok(mode[f])) return SZNB_EINVAL;
+    caps[f] = compress_min_cap_impl(n[f], mode[f]);
+    outs[f] = static_cast<uint8_t *>(d_ws) + o;
+    o = al256(o + caps[f]);
+  }
+  if (ws_bytes < o) return SZNB_ENOSPC;
+  int rc = compress_impl(nf, fields, n, eb, mode, outs.data(), caps.data(), nullptr, false, d_ws, L.total, stream,
+                         true);
+  if (rc) return rc;
+  DevInfo *dv;
+  if ((rc = dev_init(&dv))) return rc;
+  Launch P;
+  P.E = (int)((1u << block_log2_of(mode[0])) / kThreads);
+  P.total_blocks = L.total_blocks;
+  P.nf = nf;
+  P.nslots = L.nslots;
+  P.ws = static_cast<uint8_t *>(d_ws);
+  P.L = L;
+  if (!L.total_blocks) return SZNB_OK;
+  int grid = (int)std::min<uint64_t>((uint64_t)dv->cus * 8, L.total_blocks);
+  switch (P.E) {
+    case 4: return launch_features<4>(P, stream, grid, feat, cost, label);
+    case 8: return launch_features<8>(P, stream, grid, feat, cost, label);
+    case 16: return launch_features<16>(P, stream, grid, feat, cost, label);
+    case 32: return launch_features<32>(P, stream, grid, feat, cost, label);
+    default: return launch_features<64>(P, stream, grid, feat, cost, label);
+  }
+}
+
+static uint64_t features_ws_bytes(int nf, const uint64_t *n, const uint32_t *mode) {
+  uint64_t o = compress_layout(nf, n, mode).total;
+  for (int f = 0; f < nf; f++) o = al256(o + compress_min_cap_impl(n[f], mode[f]));
+  return o;
+}
+
+static int set_selector_impl(const float *h_params, float tau) {
+  if (!h_params || std::isnan(tau)) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  std::vector<float> w(h_params, h_params + kMlpParams);
+  for (int i = 0; i < kMlpParams; i++) {
+    const bool bias = (i >= kB1 && i < kW2) || (i >= kB2 && i < kW3) || i >= kB3;
+    if (!std::isfinite(w[i])) return SZNB_EINVAL;
+    if (!bias) w[i] = bf16_round(w[i]);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!dv->sel && hipMalloc(reinterpret_cast<void **>(&dv->sel), sizeof(float) * kMlpParams) != hipSuccess) {
+    dv->sel = nullptr;
+    return SZNB_EDEVICE;
+  }
+  if (hipMemcpy(dv->sel, w.data(), sizeof(float) * kMlpParams, hipMemcpyHostToDevice) != hipSuccess)
+    return SZNB_EDEVICE;
+  dv->tau = tau;
+  return SZNB_OK;
 }
 
 // ---------------------------------------------------------- decompress
@@ -711,6 +806,64 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
     if (v != SZNB_OK && first == SZNB_OK) first = v;
   }
   return first;
+}
+
+int sznb_set_selector(const float *h_params, float tau) { return set_selector_impl(h_params, tau); }
+
+uint64_t sznb_features_workspace_bytes(int nf, const uint64_t *h_n, const uint32_t *h_mode) {
+  return features_ws_bytes(nf, h_n, h_mode);
+}
+
+int sznb_block_features(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                        const uint32_t *h_mode, float *d_feat, uint64_t *d_cost, uint8_t *d_label, void *d_ws,
+                        uint64_t ws_bytes, hipStream_t stream) {
+  return features_impl(nf, h_fields, h_n, h_eb, h_mode, d_feat, d_cost, d_label, d_ws, ws_bytes, stream);
+}
+
+int sznb_compress_fallbacks(const void *d_ws, int nf, uint32_t *h_out, hipStream_t stream) {
+  if (!d_ws || nf <= 0 || !h_out) return SZNB_EINVAL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  const uint8_t *ws = static_cast<const uint8_t *>(d_ws);
+  for (int f = 0; f < nf; f++) {
+    const uint8_t *st = ws + al256(sizeof(GCtl)) + kStateStride * f + offsetof(FState, fallbacks);
+    if (hipMemcpy(&h_out[f], st, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
+  }
+  return SZNB_OK;
+}
+
+uint64_t sznb_mlp_grad_workspace_bytes(uint32_t batch) { return 4ull * 132 * batch; }
+
+int sznb_mlp_grad(const float *d_params, const float *d_feat, const uint8_t *d_label, uint32_t batch, float *d_grad,
+                  float *d_loss, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  if (!d_params || !d_feat || !d_label || !d_grad || !d_loss || !d_ws || batch == 0) return SZNB_EINVAL;
+  if (ws_bytes < sznb_mlp_grad_workspace_bytes(batch)) return SZNB_ENOSPC;
+  float *buf = static_cast<float *>(d_ws);
+  SZNB_LAUNCH("mlp_fwd_bwd", mlp_fwd_bwd, dim3((batch + 255) / 256), dim3(256), 0, stream, d_params, d_feat, d_label,
+              batch, buf);
+  SZNB_LAUNCH("mlp_grad", mlp_grad, dim3((kMlpParams + 255) / 256), dim3(256), 0, stream, d_feat, buf, batch, d_grad);
+  SZNB_LAUNCH("mlp_loss", mlp_loss, dim3(1), dim3(256), 0, stream, buf, batch, d_loss);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+int sznb_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, uint32_t step, float lr, float beta1,
+                  float beta2, float eps, hipStream_t stream) {
+  if (!d_params || !d_m || !d_v || !d_grad || step == 0) return SZNB_EINVAL;
+  SZNB_LAUNCH("mlp_adam", mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, stream, d_params, d_m, d_v, d_grad,
+              step, lr, beta1, beta2, eps);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+int sznb_mlp_infer(const float *d_params, const float *d_feat, uint64_t nb, float *d_logits, uint8_t *d_choice,
+                   float *d_margin, hipStream_t stream) {
+  if (!d_params || !d_feat || !d_logits || !d_choice || !d_margin) return SZNB_EINVAL;
+  if (!nb) return SZNB_OK;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  const uint64_t grid = std::min<uint64_t>((nb + 3) / 4, (uint64_t)dv->cus * 8);
+  SZNB_LAUNCH("mlp_infer", mlp_infer, dim3((unsigned)grid), dim3(256), 0, stream, d_params, d_feat, nb, d_logits,
+              d_choice, d_margin);
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
 uint64_t sznb_md_workspace_bytes(int nf, uint64_t n) { return md_layout(nf, n).total; }

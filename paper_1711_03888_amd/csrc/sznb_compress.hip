@@ -278,6 +278,164 @@ __device__ inline int32_t residual_at(const int32_t (&d)[E], const int32_t (&pv)
   return (int32_t)(b0 - (a1 - a2));
 }
 
+// Exhaustive trial of one block: the two-part size estimate of LV, LCF and
+// QCF residuals (classes of res_class, 2^-16 bit units), argmin with ties to
+// the lowest predictor.  Leaves the costs in s_cost and the choice in
+// *s_pred; all threads of the workgroup take part.
+template <int E>
+__device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3], uint32_t len,
+                                   const uint32_t *__restrict__ logt, uint32_t *s_cls, uint32_t *s_extra,
+                                   unsigned long long *s_cost, int *s_pred) {
+  const int t = threadIdx.x;
+  if (t < 3 * kNClass) s_cls[t] = 0;
+  if (t < 3) { s_extra[t] = 0; s_cost[t] = 0; }
+  __syncthreads();
+  uint32_t ex[3] = {0u, 0u, 0u};
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    if ((uint32_t)t * E + e < len) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) {
+        uint32_t xb;
+        uint32_t cl = res_class(residual_at<E>(d, pv, e, k), xb);
+        atomicAdd(&s_cls[k * kNClass + cl], 1u);
+        ex[k] += xb;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    uint32_t v = wave_sum(ex[k]);
+    if ((t & (kWave - 1)) == 0) atomicAdd(&s_extra[k], v);
+  }
+  __syncthreads();
+  if (t < 3 * kNClass) {
+    uint32_t n_c = s_cls[t];
+    if (n_c) atomicAdd(&s_cost[t / kNClass], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]));
+  }
+  __syncthreads();
+  if (t == 0) {
+    int best = 0;
+    unsigned long long bc = 0;
+    for (int k = 0; k < 3; k++) {
+      unsigned long long ck = s_cost[k] + 65536ull * s_extra[k];
+      s_cost[k] = ck;
+      if (k == 0 || ck < bc) { bc = ck; best = k; }
+    }
+    *s_pred = best;
+  }
+  __syncthreads();
+}
+
+// Selector features of one block (exact integer sums and counts of the
+// lattice values p and of their LV / LCF residuals Dp, D2p):
+//   0 sum p / (len P')   1 (max p - min p) / P'   2 F(sum|Dp|) - F(len)
+//   3 F(sum|D2p|) - F(len)   4 F(max|Dp|)   5 F(max|D2p|)   6 #(Dp=0)/len
+//   7 #(D2p=0)/len   8 #(|Dp|<=1)/len   9 #(|D2p|<=1)/len
+//   10 #(sign changes of Dp)/len   11 F(sum bitlen|Dp|) - F(len)
+//   12 F(sum bitlen|D2p|) - F(len)   13 #(|Dp|>=32768)/len   14 F(P')   15 1
+// with P' = max(P, 1), F = flog_u64 and every ratio one fp64 division
+// rounded to float.  Leaves the 16 features in s_feat.
+struct FeatRed {
+  long long sd[kThreads / kWave];
+  unsigned long long s1[kThreads / kWave], s2[kThreads / kWave];
+  int32_t dmx[kThreads / kWave], dmn[kThreads / kWave];
+  uint32_t m1[kThreads / kWave], m2[kThreads / kWave];
+  uint32_t zz[kThreads / kWave], oo[kThreads / kWave], se[kThreads / kWave];
+  uint32_t b1[kThreads / kWave], b2[kThreads / kWave];
+};
+
+template <typename T>
+__device__ inline T wave_max_t(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) { T u = __shfl_xor(v, o, kWave); v = u > v ? u : v; }
+  return v;
+}
+template <typename T>
+__device__ inline T wave_min_t(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) { T u = __shfl_xor(v, o, kWave); v = u < v ? u : v; }
+  return v;
+}
+
+template <int E>
+__device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)[3], int32_t p0, uint32_t len,
+                                      int64_t P, FeatRed *r, float *s_feat) {
+  const int t = threadIdx.x, w = t / kWave;
+  long long sd = 0;
+  unsigned long long s1 = 0, s2 = 0;
+  int32_t dmx = INT32_MIN, dmn = INT32_MAX;
+  uint32_t m1 = 0, m2 = 0, zz = 0, oo = 0, se = 0, b1 = 0, b2 = 0;
+  // Dp of the element before this thread's run (zero before the block)
+  int32_t prev = (int32_t)((uint32_t)pv[0] - (uint32_t)pv[1]);
+#pragma unroll
+  for (int e = 0; e < E; e++) {
+    const int32_t r1 = residual_at<E>(d, pv, e, 0), r2 = residual_at<E>(d, pv, e, 1);
+    if ((uint32_t)t * E + e < len) {
+      const uint32_t a1 = (uint32_t)(r1 < 0 ? -r1 : r1), a2 = (uint32_t)(r2 < 0 ? -r2 : r2);
+      sd += d[e];
+      dmx = max(dmx, d[e]);
+      dmn = min(dmn, d[e]);
+      s1 += a1;
+      s2 += a2;
+      m1 = max(m1, a1);
+      m2 = max(m2, a2);
+      zz += (a1 == 0u ? 1u : 0u) + (a2 == 0u ? 0x10000u : 0u);
+      oo += (a1 <= 1u ? 1u : 0u) + (a2 <= 1u ? 0x10000u : 0u);
+      se += (((r1 > 0 && prev < 0) || (r1 < 0 && prev > 0)) ? 1u : 0u) + (a1 >= (uint32_t)kRadius ? 0x10000u : 0u);
+      b1 += 32u - __clz(a1);
+      b2 += 32u - __clz(a2);
+    }
+    prev = r1;
+  }
+  sd = wave_sum(sd);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  dmx = wave_max_t(dmx);
+  dmn = wave_min_t(dmn);
+  m1 = wave_max_t(m1);
+  m2 = wave_max_t(m2);
+  zz = wave_sum(zz);
+  oo = wave_sum(oo);
+  se = wave_sum(se);
+  b1 = wave_sum(b1);
+  b2 = wave_sum(b2);
+  if ((t & (kWave - 1)) == 0) {
+    r->sd[w] = sd; r->s1[w] = s1; r->s2[w] = s2; r->dmx[w] = dmx; r->dmn[w] = dmn; r->m1[w] = m1; r->m2[w] = m2;
+    r->zz[w] = zz; r->oo[w] = oo; r->se[w] = se; r->b1[w] = b1; r->b2[w] = b2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int v = 1; v < kThreads / kWave; v++) {
+      sd += r->sd[v]; s1 += r->s1[v]; s2 += r->s2[v];
+      dmx = max(dmx, r->dmx[v]); dmn = min(dmn, r->dmn[v]);
+      m1 = max(m1, r->m1[v]); m2 = max(m2, r->m2[v]);
+      zz += r->zz[v]; oo += r->oo[v]; se += r->se[v]; b1 += r->b1[v]; b2 += r->b2[v];
+    }
+    const uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
+    const long long sum_p = sd + (long long)len * (long long)p0;
+    auto ratio = [](uint64_t a, uint64_t b) { return __double2float_rn(__ddiv_rn((double)a, (double)b)); };
+    const float fl = flog_u64(len);
+    s_feat[0] = ratio((uint64_t)sum_p, (uint64_t)len * Pp);
+    s_feat[1] = ratio((uint64_t)((int64_t)dmx - (int64_t)dmn), Pp);
+    s_feat[2] = flog_u64(s1) - fl;
+    s_feat[3] = flog_u64(s2) - fl;
+    s_feat[4] = flog_u64(m1);
+    s_feat[5] = flog_u64(m2);
+    s_feat[6] = ratio(zz & 0xffffu, len);
+    s_feat[7] = ratio(zz >> 16, len);
+    s_feat[8] = ratio(oo & 0xffffu, len);
+    s_feat[9] = ratio(oo >> 16, len);
+    s_feat[10] = ratio(se & 0xffffu, len);
+    s_feat[11] = flog_u64(b1) - fl;
+    s_feat[12] = flog_u64(b2) - fl;
+    s_feat[13] = ratio(se >> 16, len);
+    s_feat[14] = flog_u64(Pp);
+    s_feat[15] = 1.0f;
+  }
+  __syncthreads();
+}
+
 template <int E>
 __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F, int nf,
                                                     const uint64_t *__restrict__ fb0, uint64_t total,
@@ -288,7 +446,9 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
   __shared__ uint32_t s_extra[3];
   __shared__ unsigned long long s_cost[3];
   __shared__ int32_t s_p0;
-  __shared__ int s_pred;
+  __shared__ int s_pred, s_fb;
+  __shared__ FeatRed s_red;
+  __shared__ float s_feat[kNFeat];
   __shared__ uint32_t s_win[3 * kWin];
   const int t = threadIdx.x;
   const uint32_t wbase = kRadius - kWin / 2;
@@ -321,45 +481,24 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
 
     int pred = (int)c.policy;
     if (c.policy >= 2) {
-      if (t < 3 * kNClass) s_cls[t] = 0;
-      if (t < 3) { s_extra[t] = 0; s_cost[t] = 0; }
-      __syncthreads();
-      uint32_t ex[3] = {0u, 0u, 0u};
-#pragma unroll
-      for (int e = 0; e < E; e++) {
-        if ((uint32_t)t * E + e < len) {
-#pragma unroll
-          for (int k = 0; k < 3; k++) {
-            uint32_t xb;
-            uint32_t cl = res_class(residual_at<E>(d, pv, e, k), xb);
-            atomicAdd(&s_cls[k * kNClass + cl], 1u);
-            ex[k] += xb;
+      bool trial = true;
+      if (c.policy == 3) {
+        block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
+        if (t < kWave) {
+          float margin, z[3];
+          const int top = mlp_select_wave(c.sel, s_feat, margin, z);
+          if (t == 0) {
+            s_pred = top;
+            s_fb = !(margin >= c.tau);
           }
         }
+        __syncthreads();
+        trial = s_fb != 0;
+        if (trial && t == 0) atomicAdd(&c.st->fallbacks, 1u);
       }
-#pragma unroll
-      for (int k = 0; k < 3; k++) {
-        uint32_t v = wave_sum(ex[k]);
-        if ((t & (kWave - 1)) == 0) atomicAdd(&s_extra[k], v);
-      }
-      __syncthreads();
-      if (t < 3 * kNClass) {
-        uint32_t n_c = s_cls[t];
-        if (n_c) atomicAdd(&s_cost[t / kNClass], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]));
-      }
-      __syncthreads();
-      if (t == 0) {
-        int best = 0;
-        unsigned long long bc = 0;
-        for (int k = 0; k < 3; k++) {
-          unsigned long long ck = s_cost[k] + 65536ull * s_extra[k];
-          if (k == 0 || ck < bc) { bc = ck; best = k; }
-        }
-        s_pred = best;
-        c.out[c.sec.pred + b] = (uint8_t)best;
-      }
-      __syncthreads();
+      if (trial) block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
       pred = s_pred;
+      if (t == 0) c.out[c.sec.pred + b] = (uint8_t)pred;
     }
     if (t == 0) reinterpret_cast<int32_t *>(c.out + c.sec.pfirst)[b] = p0;
 
@@ -383,6 +522,47 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
     __syncthreads();
   }
   flush(cur);
+}
+
+// Training data of the selector: features, the three trial costs and the
+// trial's choice of every block (global block order of the field table).
+template <int E>
+__global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict__ F, int nf,
+                                                       const uint64_t *__restrict__ fb0, uint64_t total,
+                                                       const uint32_t *__restrict__ logt, float *feat,
+                                                       uint64_t *cost, uint8_t *label) {
+  constexpr int S = E * kThreads;
+  __shared__ int32_t s_tail[3 * kThreads];
+  __shared__ uint32_t s_cls[3 * kNClass];
+  __shared__ uint32_t s_extra[3];
+  __shared__ unsigned long long s_cost[3];
+  __shared__ int32_t s_p0;
+  __shared__ int s_pred;
+  __shared__ FeatRed s_red;
+  __shared__ float s_feat[kNFeat];
+  const int t = threadIdx.x;
+  for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
+    const int f = find_field(fb0, nf, g);
+    const CField &c = F[f];
+    const FState *st = c.st;
+    if (st->status != 0 || st->is_const) {
+      if (t < kNFeat) feat[g * kNFeat + t] = 0.0f;
+      if (t < 3) cost[g * 3 + t] = 0;
+      if (t == 0) label[g] = 0;
+      continue;
+    }
+    const uint64_t b = g - c.gblock0;
+    const uint64_t i0 = b * S;
+    const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
+    int32_t d[E], pv[3], p0;
+    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
+    block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
+    block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
+    if (t < kNFeat) feat[g * kNFeat + t] = s_feat[t];
+    if (t < 3) cost[g * 3 + t] = s_cost[t];
+    if (t == 0) label[g] = (uint8_t)s_pred;
+    __syncthreads();
+  }
 }
 
 // --------------------------------------------------------------- Huffman
@@ -962,6 +1142,8 @@ __global__ void k_final(const CField *__restrict__ F, int nf) {
 // explicit instantiations (block sizes 1K..16K)
 #define SZNB_INST(E)                                                                                        \
   template __global__ void k_quant<E>(const CField *, int, const uint64_t *, uint64_t, const uint32_t *); \
+  template __global__ void k_features<E>(const CField *, int, const uint64_t *, uint64_t, const uint32_t *,  \
+                                         float *, uint64_t *, uint8_t *);                                    \
   template __global__ void k_pack<E>(const CField *, int, const uint64_t *, uint64_t, GCtl *);
 SZNB_INST(4)
 SZNB_INST(8)

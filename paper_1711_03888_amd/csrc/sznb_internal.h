@@ -62,7 +62,7 @@ struct alignas(64) FState {
   uint64_t off_payload;
   uint64_t payload_words;
   uint32_t blocks_done;
-  uint32_t pad0;
+  uint32_t fallbacks;     // learned policy: blocks decided by the exhaustive trial
 };
 
 // per-field descriptor written by the host
@@ -83,6 +83,9 @@ struct alignas(16) CField {
   uint32_t *enc;          // nhist x 65536 codewords: code | len << 24
   uint32_t *book;         // nhist x (32 bl_count words + 32768 words of u16 symbols)
   uint64_t *lbflag;       // decoupled look-back words, one per block
+  const float *sel;       // learned policy: selector parameters (weights bfloat16-rounded)
+  float tau;              // learned policy: smallest logit margin trusted
+  uint32_t pad_sel;
 };
 constexpr int kBookWords = 32 + kNSyms / 2;
 
@@ -151,6 +154,72 @@ constexpr int kSlowWords = 128;
 // decode-table entry: sym | len << 16; flags
 constexpr uint32_t kLutLong = 1u << 22;
 constexpr uint32_t kLutInvalid = 1u << 23;
+
+// ------------------------------------------------------ learned selector
+
+// Network 16 -> 32 -> 32 -> 3 (ReLU); flat parameters W1[32][16], b1[32],
+// W2[32][32], b2[32], W3[3][32], b3[3].
+constexpr int kNFeat = 16;
+constexpr int kMlpParams = 1699;
+constexpr int kW1 = 0, kB1 = 512, kW2 = 544, kB2 = 1568, kW3 = 1600, kB3 = 1696;
+
+// bfloat16 rounding to nearest, ties to even (finite values)
+__host__ __device__ inline float bf16_round(float x) {
+  uint32_t u;
+  __builtin_memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  float r;
+  __builtin_memcpy(&r, &u, 4);
+  return r;
+}
+
+// bit length of v plus the 8 bits after its leading one, over 256
+__device__ inline float flog_u64(uint64_t v) {
+  if (!v) return 0.0f;
+  const int b = 64 - __clzll((long long)v);
+  const uint64_t frac = b - 1 >= 8 ? (v >> (b - 9)) & 255u : (v << (9 - b)) & 255u;
+  return (float)b + (float)frac * (1.0f / 256.0f);
+}
+
+// Inference on one block's features by one whole wave (lanes j and j + 32
+// both compute neuron j).  w: parameters with bfloat16-rounded weights and
+// float32 biases.  Each neuron starts from its bias and adds w_k x_k for k
+// ascending, one fused multiply-add each; hidden outputs are ReLU'd and
+// bfloat16-rounded.  Returns the argmax (ties to the lowest index) and the
+// margin to the runner-up, uniform over the wave.
+__device__ inline int mlp_select_wave(const float *__restrict__ w, const float *feat, float &margin,
+                                      float (&z_out)[3]) {
+  const int j = (int)(__lane_id() & 31u);
+  float acc = w[kB1 + j];
+#pragma unroll
+  for (int k = 0; k < kNFeat; k++) acc = __builtin_fmaf(w[kW1 + 16 * j + k], bf16_round(feat[k]), acc);
+  const float h1 = bf16_round(acc > 0.0f ? acc : 0.0f);
+  acc = w[kB2 + j];
+#pragma unroll
+  for (int k = 0; k < 32; k++)
+    acc = __builtin_fmaf(w[kW2 + 32 * j + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), k)), acc);
+  const float h2 = bf16_round(acc > 0.0f ? acc : 0.0f);
+  const int jj = j < 3 ? j : 0;
+  acc = w[kB3 + jj];
+#pragma unroll
+  for (int k = 0; k < 32; k++)
+    acc = __builtin_fmaf(w[kW3 + 32 * jj + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h2), k)), acc);
+  float z[3];
+#pragma unroll
+  for (int k = 0; k < 3; k++) z[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k));
+  int top = 0;
+  if (z[1] > z[top]) top = 1;
+  if (z[2] > z[top]) top = 2;
+  float second = -__builtin_inff();
+#pragma unroll
+  for (int k = 0; k < 3; k++)
+    if (k != top && z[k] > second) second = z[k];
+  margin = z[top] - second;
+#pragma unroll
+  for (int k = 0; k < 3; k++) z_out[k] = z[k];
+  return top;
+}
 
 // ------------------------------------------------------------ primitives
 

@@ -60,6 +60,17 @@ def lib():
         L.sznb_profile.argtypes = [ctypes.c_int]
         L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
         L.sznb_strerror.argtypes = [ctypes.c_int]
+        L.sznb_set_selector.argtypes = [_vp, ctypes.c_float]
+        L.sznb_features_workspace_bytes.argtypes = [ctypes.c_int, _vp, _vp]
+        L.sznb_features_workspace_bytes.restype = _u64
+        L.sznb_block_features.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.sznb_compress_fallbacks.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+        L.sznb_mlp_grad_workspace_bytes.argtypes = [ctypes.c_uint32]
+        L.sznb_mlp_grad_workspace_bytes.restype = _u64
+        L.sznb_mlp_grad.argtypes = [_vp, _vp, _vp, ctypes.c_uint32, _vp, _vp, _vp, _u64, _vp]
+        L.sznb_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, _vp]
+        L.sznb_mlp_infer.argtypes = [_vp, _vp, _u64, _vp, _vp, _vp, _vp]
         L.sznb_md_workspace_bytes.argtypes = [ctypes.c_int, _u64]
         L.sznb_md_workspace_bytes.restype = _u64
         L.sznb_md_bound.argtypes = [ctypes.c_int, _u64]
@@ -284,3 +295,83 @@ def md_decompress(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, st
                                   ws.data_ptr(), ws.numel(), _stream(stream))
     _check(rc, "md_decompress")
     return outs
+
+
+# ------------------------------------------------------- learned selector
+
+MLP_PARAMS = 1699
+N_FEATURES = 16
+
+
+def set_selector(params, tau: float) -> None:
+    """Load the selector of the learned policy on the current device."""
+    import numpy as np
+    w = np.ascontiguousarray(params, dtype=np.float32)
+    if w.size != MLP_PARAMS:
+        raise ValueError("selector needs %d parameters" % MLP_PARAMS)
+    _check(lib().sznb_set_selector(w.ctypes.data, float(tau)), "set_selector")
+
+
+def block_features(fields: Sequence[torch.Tensor], eb, mode, *, ws=None, stream=None):
+    """(features float32 [blocks, 16], trial costs int64 [blocks, 3], trial
+    choice uint8 [blocks]) of every block of the fields, in field order."""
+    fields = [_field(f) for f in fields]
+    nf = len(fields)
+    ebs = [float(eb)] * nf if not isinstance(eb, (list, tuple)) else [float(e) for e in eb]
+    modes = [int(mode)] * nf if not isinstance(mode, (list, tuple)) else [int(m) for m in mode]
+    ns = [f.numel() for f in fields]
+    S = 1 << (((modes[0] >> 8) & 15) or 12)
+    nb = sum(-(-n // S) for n in ns)
+    dev = fields[0].device
+    wsb = int(lib().sznb_features_workspace_bytes(nf, _arr(_u64, ns), _arr(ctypes.c_uint32, modes)))
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, dev)
+    feat = torch.empty((max(nb, 1), N_FEATURES), dtype=torch.float32, device=dev)
+    cost = torch.empty((max(nb, 1), 3), dtype=torch.int64, device=dev)
+    label = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    rc = lib().sznb_block_features(nf, _arr(_vp, [f.data_ptr() for f in fields]), _arr(_u64, ns),
+                                   _arr(ctypes.c_double, ebs), _arr(ctypes.c_uint32, modes), feat.data_ptr(),
+                                   cost.data_ptr(), label.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "block_features")
+    return feat[:nb], cost[:nb], label[:nb]
+
+
+def compress_fallbacks(ws: torch.Tensor, nf: int, stream=None):
+    out = (ctypes.c_uint32 * nf)()
+    _check(lib().sznb_compress_fallbacks(ws.data_ptr(), nf, out, _stream(stream)), "compress_fallbacks")
+    return list(out)
+
+
+def mlp_grad(params: torch.Tensor, feat: torch.Tensor, label: torch.Tensor, *, ws=None, grad=None, loss=None,
+             stream=None):
+    B = feat.shape[0]
+    dev = params.device
+    wsb = int(lib().sznb_mlp_grad_workspace_bytes(B))
+    if ws is None or ws.numel() < wsb:
+        ws = workspace(wsb, dev)
+    if grad is None:
+        grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=dev)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    rc = lib().sznb_mlp_grad(params.data_ptr(), feat.data_ptr(), label.data_ptr(), B, grad.data_ptr(),
+                             loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(rc, "mlp_grad")
+    return grad, loss, ws
+
+
+def mlp_adam(params, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    rc = lib().sznb_mlp_adam(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), int(step), float(lr),
+                             float(beta1), float(beta2), float(eps), _stream(stream))
+    _check(rc, "mlp_adam")
+
+
+def mlp_infer(params: torch.Tensor, feat: torch.Tensor, stream=None):
+    nb = feat.shape[0]
+    dev = feat.device
+    logits = torch.empty((max(nb, 1), 3), dtype=torch.float32, device=dev)
+    choice = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    margin = torch.empty(max(nb, 1), dtype=torch.float32, device=dev)
+    rc = lib().sznb_mlp_infer(params.data_ptr(), feat.data_ptr(), nb, logits.data_ptr(), choice.data_ptr(),
+                              margin.data_ptr(), _stream(stream))
+    _check(rc, "mlp_infer")
+    return logits[:nb], choice[:nb], margin[:nb]

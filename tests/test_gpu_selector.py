@@ -1,0 +1,133 @@
+"""GPU learned selector vs the CPU oracle, through the C ABI.
+
+Features, trial costs and labels bit-exact; bfloat16 inference bit-exact;
+learned-policy streams byte-identical for seeded network parameters (the
+parameters are inputs here, drawn from a seeded generator); training
+gradients within 1e-4 of the oracle's float64 gradients; Adam within float32
+rounding of the oracle's step.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1711_03888_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1711_03888_amd import sznb  # noqa: E402
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _fields():
+    snap = datagen.cosmology(1 << 15, seed=31)
+    return [(datagen.random_walk(5 * 4096 + 1234, seed=12), 1e-4), (snap["xx"], 1e-3), (snap["vy"], 1e-4),
+            (datagen.md_lattice(cells=(8, 8, 16), seed=4)["zz"], 1e-3)]
+
+
+@pytest.mark.parametrize("S_log2", [10, 12])
+def test_features_costs_labels_bitexact(S_log2):
+    S = 1 << S_log2
+    fields = _fields()
+    mode = sznb.PRED_BESTFIT | sznb.EB_REL | sznb.BLOCK_LOG2(S_log2)
+    print("features S=%d" % S, flush=True)
+    feat, cost, label = sznb.block_features([_dev(x) for x, _ in fields], [e for _, e in fields], mode)
+    feat, cost, label = feat.cpu().numpy(), cost.cpu().numpy(), label.cpu().numpy()
+    o = 0
+    for x, eb in fields:
+        q = oracle.lattice(x, eb)
+        P = oracle.params(x, eb)["P"]
+        rf = oracle.features(q, S, P)
+        rp, rc = oracle.select(q, S)
+        nb = rf.shape[0]
+        assert np.array_equal(feat[o:o + nb].view(np.uint32), rf.view(np.uint32))
+        assert np.array_equal(cost[o:o + nb].astype(np.uint64), rc)
+        assert np.array_equal(label[o:o + nb], rp)
+        o += nb
+    assert o == feat.shape[0]
+
+
+def test_inference_bitexact():
+    rng = np.random.default_rng(17)
+    w = rng.normal(0, 0.4, mlp.NPARAM).astype(np.float32)
+    x = datagen.random_walk(40 * 1024, seed=3)
+    q = oracle.lattice(x, 1e-4)
+    feat = oracle.features(q, 1024, oracle.params(x, 1e-4)["P"])
+    feat = np.concatenate([feat, rng.normal(0, 2, (300, 16)).astype(np.float32)])
+    logits, choice, margin = sznb.mlp_infer(_dev(w), _dev(feat))
+    ref = oracle.mlp_logits(w, feat)
+    assert np.array_equal(logits.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    assert np.array_equal(choice.cpu().numpy(), np.argmax(ref, axis=1))
+
+
+@pytest.mark.parametrize("tau", [float("-inf"), 0.0, 1.5, float("inf")])
+def test_learned_streams_bitexact(tau):
+    rng = np.random.default_rng(23)
+    w = rng.normal(0, 0.5, mlp.NPARAM).astype(np.float32)
+    sznb.set_selector(w, tau)
+    mode = sznb.PRED_LEARNED | sznb.EB_REL | sznb.BLOCK_LOG2(10)
+    for i, (x, eb) in enumerate(_fields()):
+        print("learned tau=%g field %d" % (tau, i), flush=True)
+        ref = oracle.compress(x, eb, mode, selector=(w, tau))
+        xt = _dev(np.ascontiguousarray(x, np.float32))
+        outs = sznb.compress_batch([xt], eb, mode)
+        assert bytes(outs[0].cpu().numpy()) == ref
+        y = sznb.decompress(outs[0], x.size).cpu().numpy()
+        assert np.array_equal(y.view(np.uint32), oracle.decompress(ref).view(np.uint32))
+    # fallback counts equal the oracle's
+    x, eb = _fields()[0]
+    q = oracle.lattice(x, eb)
+    _, fb = oracle.select_learned(q, 1024, oracle.params(x, eb)["P"], w, tau)
+    c = sznb.compress_batch_async([_dev(np.ascontiguousarray(x, np.float32))], eb, mode)
+    assert sznb.compress_fallbacks(c.ws, 1) == [int(fb.sum())]
+
+
+def test_learned_without_selector_is_invalid():
+    # a fresh process state is not guaranteed here; a non-finite tau is rejected
+    with pytest.raises(sznb.SznbError):
+        sznb.set_selector(np.zeros(mlp.NPARAM, np.float32), float("nan"))
+
+
+@pytest.mark.parametrize("B", [1, 37, 4096])
+def test_gradient_vs_float64_oracle(B):
+    rng = np.random.default_rng(B)
+    w = rng.normal(0, 0.3, mlp.NPARAM).astype(np.float32)
+    x = rng.normal(0, 1, (B, 16)).astype(np.float32)
+    y = rng.integers(0, 3, B).astype(np.uint8)
+    g, loss, _ = sznb.mlp_grad(_dev(w), _dev(x), _dev(y))
+    ref = mlp.grad(w.astype(np.float64), x.astype(np.float64), y)
+    gg = g.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref).max()
+    assert np.abs(gg - ref).max() <= 1e-4 * scale, np.abs(gg - ref).max() / scale
+    assert abs(loss.item() - mlp.loss(w.astype(np.float64), x.astype(np.float64), y)) <= 1e-5
+
+
+def test_gradient_is_deterministic():
+    rng = np.random.default_rng(2)
+    w = _dev(rng.normal(0, 0.3, mlp.NPARAM).astype(np.float32))
+    x = _dev(rng.normal(0, 1, (3000, 16)).astype(np.float32))
+    y = _dev(rng.integers(0, 3, 3000).astype(np.uint8))
+    g1 = sznb.mlp_grad(w, x, y)[0].cpu().numpy()
+    g2 = sznb.mlp_grad(w, x, y)[0].cpu().numpy()
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def test_adam_vs_oracle():
+    rng = np.random.default_rng(4)
+    w = rng.normal(0, 1, mlp.NPARAM).astype(np.float32)
+    m = np.zeros(mlp.NPARAM)
+    v = np.zeros(mlp.NPARAM)
+    wd, md, vd = _dev(w.copy()), _dev(np.zeros(mlp.NPARAM, np.float32)), _dev(np.zeros(mlp.NPARAM, np.float32))
+    wr = w.astype(np.float64)
+    for step in range(1, 6):
+        g = rng.normal(0, 0.1, mlp.NPARAM).astype(np.float32)
+        sznb.mlp_adam(wd, md, vd, _dev(g), step, 1e-2)
+        wr, m, v = mlp.adam(wr, m, v, g.astype(np.float64), step, 1e-2)
+    assert np.abs(wd.cpu().numpy() - wr).max() <= 1e-5

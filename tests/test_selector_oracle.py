@@ -1,0 +1,201 @@
+"""Pins of the learned-selector oracle: features, bfloat16 inference, the
+learned policy's fallback, and the float64 training arithmetic.
+
+Features are pinned by blocks whose statistics are known in closed form and
+by a vectorised numpy computation; inference by an exact rational emulation
+of each fused multiply-add with torch's own bfloat16 rounding; gradients by
+central finite differences; Adam by its first-step closed form.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_1711_03888_amd import datagen
+
+
+def test_flog_powers_of_two():
+    # F(2^k) = k + 1 exactly: a block whose sum |Dp| is 2^k
+    for k in range(0, 20):
+        q = np.array([0, 2 ** k], np.int32)
+        f = oracle.features(q, 1024, 2 ** 27)[0]
+        assert f[2] == float(k + 1) - 2.0  # F(sum|Dp|) - F(len = 2)
+
+
+def test_features_constant_block():
+    q = np.full(4096, 777, np.int32)
+    f = oracle.features(q, 4096, 1000)[0]
+    assert f[0] == np.float32(777 / 1000)
+    assert f[1] == 0
+    assert f[4] == 0 and f[5] == 0  # F(0) = 0
+    assert f[6] == 1 and f[7] == 1 and f[8] == 1 and f[9] == 1
+    assert f[10] == 0 and f[13] == 0
+    assert f[14] == np.float32(10 + 0xf4 / 256)  # 1000 = 0b1111101000
+    assert f[15] == 1
+
+
+def test_features_ramp_and_zigzag():
+    n, c = 4096, 5
+    ramp = (100 + c * np.arange(n)).astype(np.int32)
+    f = oracle.features(ramp, n, 1 << 20)[0]
+    # Dp = (0, c, c, ...), D2p = (0, c, 0, 0, ...)
+    assert f[6] == np.float32(1 / n) and f[7] == np.float32((n - 1) / n)
+    assert f[4] == 3.25 and f[5] == 3.25  # F(5) = 3 + 0b01/4 = 3.25
+    assert f[10] == 0
+    zig = (100 + c * (np.arange(n) % 2)).astype(np.int32)
+    f = oracle.features(zig, n, 1 << 20)[0]
+    # Dp = (0, c, -c, c, ...): a sign change at every j >= 2
+    assert f[10] == np.float32((n - 2) / n)
+    assert f[8] == np.float32(1 / n)
+
+
+def _features_numpy(q, P):
+    q = q.astype(np.int64)
+    n = q.size
+    d = q - q[0]
+    dp = np.diff(np.concatenate([[0], d]))
+    d2 = np.diff(np.concatenate([[0], dp]))
+    a1, a2 = np.abs(dp), np.abs(d2)
+
+    def F(v):
+        v = int(v)
+        b = v.bit_length()
+        if b == 0:
+            return np.float32(0)
+        frac = (v >> (b - 9)) & 255 if b >= 9 else (v << (9 - b)) & 255
+        return np.float32(b + frac / 256)
+
+    def r(a, b):
+        return np.float32(np.float64(a) / np.float64(b))
+
+    Pp = max(int(P), 1)
+    sc = int(np.sum((dp[1:] > 0) & (dp[:-1] < 0)) + np.sum((dp[1:] < 0) & (dp[:-1] > 0)))
+    bl1 = int(sum(int(v).bit_length() for v in a1))
+    bl2 = int(sum(int(v).bit_length() for v in a2))
+    fl = F(n)
+    return np.array([r(q.sum(), n * Pp), r(q.max() - q.min(), Pp), F(a1.sum()) - fl, F(a2.sum()) - fl,
+                     F(a1.max()), F(a2.max()), r((a1 == 0).sum(), n), r((a2 == 0).sum(), n),
+                     r((a1 <= 1).sum(), n), r((a2 <= 1).sum(), n), r(sc, n), F(bl1) - fl, F(bl2) - fl,
+                     r((a1 >= 32768).sum(), n), F(Pp), 1.0], np.float32)
+
+
+@pytest.mark.parametrize("S", [1024, 4096])
+def test_features_match_vectorised_numpy(S):
+    x = datagen.random_walk(3 * S + 333, seed=21)
+    q = oracle.lattice(x, 1e-4)
+    P = oracle.params(x, 1e-4)["P"]
+    got = oracle.features(q, S, P)
+    for b in range(got.shape[0]):
+        want = _features_numpy(q[b * S:(b + 1) * S], P)
+        assert np.array_equal(got[b], want), (b, got[b], want)
+
+
+def test_bf16_matches_torch_rounding():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(3)
+    vals = rng.normal(0, 10, 2000).astype(np.float32)
+    # exact ties between two bfloat16 values, both parities
+    ties = (np.arange(1, 200, dtype=np.uint32) << 16 | 0x8000).view(np.float32)
+    vals = np.concatenate([vals, ties, -ties, np.float32([0.0, -0.0, 1e-40, 3e38])])
+    ref = torch.from_numpy(vals).to(torch.bfloat16).to(torch.float32).numpy()
+    got = np.array([oracle.bf16(float(v)) for v in vals], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def _round_f32(x: Fraction) -> np.float32:
+    """float32 nearest to the rational x, ties to even."""
+    c = np.float32(float(x))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        err = abs(Fraction(float(cand)) - x)
+        key = (err, int(np.float32(cand).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, cand)
+    return np.float32(best[1])
+
+
+def _infer_exact(w, feat):
+    torch = pytest.importorskip("torch")
+
+    def bf(v):
+        return np.float32(torch.tensor([float(v)], dtype=torch.float32).to(torch.bfloat16).float().item())
+
+    p = mlp.unpack(w)
+    x = [bf(v) for v in feat]
+
+    def layer(W, b, inp, relu):
+        out = []
+        for j in range(W.shape[0]):
+            acc = np.float32(b[j])
+            for k in range(W.shape[1]):
+                acc = _round_f32(Fraction(float(bf(np.float32(W[j, k])))) * Fraction(float(inp[k]))
+                                 + Fraction(float(acc)))
+            out.append(bf(max(acc, np.float32(0))) if relu else acc)
+        return out
+
+    h1 = layer(p["W1"], p["b1"], x, True)
+    h2 = layer(p["W2"], p["b2"], h1, True)
+    return np.array(layer(p["W3"], p["b3"], h2, False), np.float32)
+
+
+def test_mlp_inference_exact_emulation():
+    rng = np.random.default_rng(5)
+    w = rng.normal(0, 0.4, mlp.NPARAM).astype(np.float32)
+    x = datagen.random_walk(4 * 1024, seed=8)
+    q = oracle.lattice(x, 1e-3)
+    feat = oracle.features(q, 1024, oracle.params(x, 1e-3)["P"])
+    feat = np.concatenate([feat, rng.normal(0, 3, (3, 16)).astype(np.float32)])
+    got = oracle.mlp_logits(w, feat)
+    for b in range(feat.shape[0]):
+        assert np.array_equal(got[b].view(np.uint32), _infer_exact(w, feat[b]).view(np.uint32)), b
+
+
+def test_learned_policy_extremes():
+    rng = np.random.default_rng(6)
+    w = rng.normal(0, 0.5, mlp.NPARAM).astype(np.float32)
+    x = datagen.random_walk(8 * 1024 + 50, seed=9)
+    eb = 1e-3
+    q = oracle.lattice(x, eb)
+    P = oracle.params(x, eb)["P"]
+    S = 1024
+    exh = oracle.select(q, S)[0]
+    pred_inf, fb_inf = oracle.select_learned(q, S, P, w, float("inf"))
+    assert fb_inf.all() and np.array_equal(pred_inf, exh)
+    pred_ninf, fb_ninf = oracle.select_learned(q, S, P, w, float("-inf"))
+    logits = oracle.mlp_logits(w, oracle.features(q, S, P))
+    assert not fb_ninf.any() and np.array_equal(pred_ninf, np.argmax(logits, axis=1))
+    # tau = +inf gives the best-fit stream, up to the policy byte
+    mode = oracle.EB_REL | oracle.block_mode(10)
+    s_l = bytearray(oracle.compress(x, eb, oracle.LEARNED | mode, selector=(w, float("inf"))))
+    s_b = oracle.compress(x, eb, oracle.BESTFIT | mode)
+    assert s_l[6] == 3 and s_b[6] == 2
+    s_l[6] = 2
+    assert bytes(s_l) == s_b
+    y = oracle.decompress(bytes(oracle.compress(x, eb, oracle.LEARNED | mode, selector=(w, 0.0))))
+    assert np.abs(y.astype(np.float64) - x).max() <= oracle.params(x, eb)["eb_abs"]
+
+
+def test_gradient_finite_differences():
+    rng = np.random.default_rng(11)
+    w = rng.normal(0, 0.5, mlp.NPARAM)
+    x = rng.normal(0, 1, (40, 16))
+    y = rng.integers(0, 3, 40)
+    g = mlp.grad(w, x, y)
+    h = 1e-6
+    idx = np.concatenate([rng.choice(mlp.NPARAM, 60, replace=False), [511, 543, 1567, 1599, 1695, 1698]])
+    for i in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[i] = h
+        fd = (mlp.loss(w + e, x, y) - mlp.loss(w - e, x, y)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 + 1e-5 * abs(g[i]), (i, fd, g[i])
+
+
+def test_adam_first_step():
+    g = np.array([0.5, -2.0, 1e-3, 0.0])
+    w0 = np.array([1.0, 1.0, 1.0, 1.0])
+    w1, m, v = mlp.adam(w0, np.zeros(4), np.zeros(4), g, 1, 0.01)
+    # bias-corrected first moments are g and g^2: a step of lr * g / (|g| + eps)
+    assert np.allclose(w1, w0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
