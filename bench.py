@@ -87,6 +87,54 @@ def md_modes(dev, eb, reps):
     return res
 
 
+def learned_section(fields, eb, block_log2, steps, bestfit_ms, bestfit_quant_ms, bestfit_ratio):
+    """The learned policy on the same snapshot: compress GB/s, ratio, fallback
+    rate, and the quantization kernel's time next to the exhaustive trial's."""
+    import torch
+
+    from paper_1711_03888_amd import selector, sznb
+    params, tau, rec = selector.load(selector.SELECTORS["nbody"])
+    sznb.set_selector(params, tau)
+    dev = fields[0].device
+    n = fields[0].numel()
+    mode = sznb.PRED_LEARNED | sznb.EB_REL | sznb.BLOCK_LOG2(block_log2)
+    caps = [sznb.compress_bound(n, mode)] * len(fields)
+    outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    lens = torch.zeros(len(fields), dtype=torch.int64, device=dev)
+    ws = sznb.workspace(sznb.compress_workspace_bytes([n] * len(fields), [mode] * len(fields)), dev)
+    run = lambda: sznb.compress_batch_async(fields, eb, mode, caps=caps, ws=ws, outs=outs, lens=lens)
+    run()
+    torch.cuda.synchronize()
+    sznb.profile(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    sznb.profile(False)
+    kern = sznb.profile_summary()
+    ms = a.elapsed_time(b) / steps
+    first, st = sznb.read_status(ws, len(fields))
+    if first != sznb.OK:
+        raise SystemExit("learned compression failed: %s" % st)
+    sizes = [int(v) for v in lens.cpu()]
+    fb = sznb.compress_fallbacks(ws, len(fields))
+    nblocks = len(fields) * -(-n // (1 << block_log2))
+    recon = sznb.decompress_batch([o[:m] for o, m in zip(outs, sizes)], [n] * len(fields))
+    for x, y, o in zip(fields, recon, outs):
+        eb_abs = sznb.stream_info(bytes(o[:128].cpu().numpy()))["eb_abs"]
+        assert (x.double() - y.double()).abs().max().item() <= eb_abs
+    ratio = 4.0 * n * len(fields) / sum(sizes)
+    qms = kern["k_quant"][0] / kern["k_quant"][1]
+    return {"compress_GBps": round(4.0 * n * len(fields) / (ms * 1e-3) / 1e9, 2), "ratio": round(ratio, 4),
+            "ratio_vs_exhaustive": round(ratio / bestfit_ratio, 5),
+            "speedup_vs_exhaustive": round(bestfit_ms / ms, 3),
+            "k_quant_ms": round(qms, 4), "k_quant_ms_exhaustive": round(bestfit_quant_ms, 4),
+            "fallback_rate": round(sum(fb) / nblocks, 5), "tau": tau,
+            "training": {k: rec.get(k) for k in ("blocks", "label_histogram", "heldout_accuracy", "data")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +147,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="values per field timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-md", action="store_true", help="skip the MD-mode measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
@@ -212,6 +261,10 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(kern.items())},
     }
+
+    if not args.no_learned and args.policy == "bestfit":
+        out["learned_selector"] = learned_section(fields, args.eb, args.block_log2, args.steps, c_ms,
+                                                  kern["k_quant"][0] / kern["k_quant"][1], ratio)
 
     if not args.no_md:
         out["md_modes"] = md_modes(dev, args.eb, 5)

@@ -123,14 +123,15 @@ const char *sznb_strerror(int status);
  * bfloat16 (nearest, ties to even), keeps biases in float32, accumulates each
  * neuron from its bias with one fused multiply-add per input in ascending
  * order, and rounds hidden outputs (after ReLU) to bfloat16.
- * Features of a block of lattice values p (length len, span P' = max(P,1)),
- * Dp / D2p its LV / LCF residuals, F(v) = bit length of v + (8 bits after the
- * leading one)/256, every ratio one fp64 division rounded to float32:
- *   0 sum p/(len P')  1 (max p - min p)/P'  2 F(sum|Dp|)-F(len)
- *   3 F(sum|D2p|)-F(len)  4 F(max|Dp|)  5 F(max|D2p|)  6 #(Dp=0)/len
- *   7 #(D2p=0)/len  8 #(|Dp|<=1)/len  9 #(|D2p|<=1)/len
- *   10 #(sign changes of Dp)/len  11 F(sum bitlen|Dp|)-F(len)
- *   12 F(sum bitlen|D2p|)-F(len)  13 #(|Dp|>=32768)/len  14 F(P')  15 1 */
+ * Features of a block of lattice values p (span P' = max(P,1)), read on its
+ * positions j = 0 mod 4 (m of them), Dp / D2p its LV / LCF residuals,
+ * F(v) = bit length of v + (8 bits after the leading one)/256, every ratio
+ * one fp64 division rounded to float32, sums and counts over the sample:
+ *   0 sum p/(m P')  1 (max p - min p)/P'  2 F(sum|Dp|)-F(m)
+ *   3 F(sum|D2p|)-F(m)  4 F(max|Dp|)  5 F(max|D2p|)  6 #(Dp=0)/m
+ *   7 #(D2p=0)/m  8 #(|Dp|<=1)/m  9 #(|D2p|<=1)/m
+ *   10 #(Dp_j Dp_{j-1} < 0)/m  11 F(sum bitlen|Dp|)-F(m)
+ *   12 F(sum bitlen|D2p|)-F(m)  13 #(|Dp|>=32768)/m  14 F(P')  15 1 */
 #define SZNB_MLP_PARAMS 1699u
 #define SZNB_FEATURES 16u
 

@@ -735,17 +735,18 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
  * methods fix one predictor each, Sec. 5.1); the definitions here are this
  * compressor's own.
  *
- * Features of a block of lattice values p_0..p_{len-1} (exact integer sums
- * and counts, so they do not depend on any summation order), with Dp_j and
- * D2p_j the LV and LCF residuals of residual() and P' = max(P, 1):
- *   0  sum p / (len P')            1  (max p - min p) / P'
- *   2  F(sum |Dp|) - F(len)        3  F(sum |D2p|) - F(len)
- *   4  F(max |Dp|)                 5  F(max |D2p|)
- *   6  #(Dp = 0) / len             7  #(D2p = 0) / len
- *   8  #(|Dp| <= 1) / len          9  #(|D2p| <= 1) / len
- *   10 #(sign changes of Dp between neighbours) / len
- *   11 F(sum bitlen |Dp|) - F(len) 12 F(sum bitlen |D2p|) - F(len)
- *   13 #(|Dp| >= 32768) / len      14 F(P)        15 1
+ * Features of a block of lattice values p_0..p_{len-1}, read on the sample
+ * J = {j < len : j = 0 mod 4} of m = |J| positions (exact integer sums and
+ * counts, so they do not depend on any summation order), with Dp_j and D2p_j
+ * the LV and LCF residuals of residual() and P' = max(P, 1):
+ *   0  sum_J p / (m P')              1  (max_J p - min_J p) / P'
+ *   2  F(sum_J |Dp|) - F(m)          3  F(sum_J |D2p|) - F(m)
+ *   4  F(max_J |Dp|)                 5  F(max_J |D2p|)
+ *   6  #_J(Dp = 0) / m               7  #_J(D2p = 0) / m
+ *   8  #_J(|Dp| <= 1) / m            9  #_J(|D2p| <= 1) / m
+ *   10 #_J(Dp_j Dp_{j-1} < 0) / m   (Dp_{-1} = 0)
+ *   11 F(sum_J bitlen |Dp|) - F(m)   12 F(sum_J bitlen |D2p|) - F(m)
+ *   13 #_J(|Dp| >= 32768) / m        14 F(P')        15 1
  * F(v) = bit length of v plus the 8 bits after its leading one, over 256 (a
  * fixed-point log2 that is exact in float32); every ratio is one fp64
  * division rounded to float32. */
@@ -767,17 +768,21 @@ static uint32_t bitlen32(uint32_t v)
     return b;
 }
 
+#define FEAT_STRIDE 4
+
 static void block_features(const int32_t *q, uint64_t len, int64_t P, float f[16])
 {
     uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
     int64_t sum_p = 0, mx = q[0], mn = q[0];
     uint64_t s1 = 0, s2 = 0, m1 = 0, m2 = 0, z1 = 0, z2 = 0, o1 = 0, o2 = 0, sc = 0, b1 = 0, b2 = 0, esc = 0;
-    int32_t prev = 0;
-    for (uint64_t j = 0; j < len; j++) {
+    uint64_t m = 0;
+    for (uint64_t j = 0; j < len; j += FEAT_STRIDE) {
+        m++;
         sum_p += q[j];
         if (q[j] > mx) mx = q[j];
         if (q[j] < mn) mn = q[j];
         int32_t d1 = residual(q, j, 0), d2 = residual(q, j, 1);
+        int32_t prev = j >= 1 ? residual(q, j - 1, 0) : 0;
         uint32_t a1 = d1 < 0 ? (uint32_t)(-(int64_t)d1) : (uint32_t)d1;
         uint32_t a2 = d2 < 0 ? (uint32_t)(-(int64_t)d2) : (uint32_t)d2;
         s1 += a1; s2 += a2;
@@ -787,27 +792,26 @@ static void block_features(const int32_t *q, uint64_t len, int64_t P, float f[16
         if (a2 == 0) z2++;
         if (a1 <= 1) o1++;
         if (a2 <= 1) o2++;
-        if (j >= 1 && ((d1 > 0 && prev < 0) || (d1 < 0 && prev > 0))) sc++;
+        if ((d1 > 0 && prev < 0) || (d1 < 0 && prev > 0)) sc++;
         b1 += bitlen32(a1);
         b2 += bitlen32(a2);
         if (a1 >= RADIUS) esc++;
-        prev = d1;
     }
-    float fl = flog(len);
-    f[0] = ratio_f((uint64_t)sum_p, len * Pp);
+    float fm = flog(m);
+    f[0] = ratio_f((uint64_t)sum_p, m * Pp);
     f[1] = ratio_f((uint64_t)(mx - mn), Pp);
-    f[2] = flog(s1) - fl;
-    f[3] = flog(s2) - fl;
+    f[2] = flog(s1) - fm;
+    f[3] = flog(s2) - fm;
     f[4] = flog(m1);
     f[5] = flog(m2);
-    f[6] = ratio_f(z1, len);
-    f[7] = ratio_f(z2, len);
-    f[8] = ratio_f(o1, len);
-    f[9] = ratio_f(o2, len);
-    f[10] = ratio_f(sc, len);
-    f[11] = flog(b1) - fl;
-    f[12] = flog(b2) - fl;
-    f[13] = ratio_f(esc, len);
+    f[6] = ratio_f(z1, m);
+    f[7] = ratio_f(z2, m);
+    f[8] = ratio_f(o1, m);
+    f[9] = ratio_f(o2, m);
+    f[10] = ratio_f(sc, m);
+    f[11] = flog(b1) - fm;
+    f[12] = flog(b2) - fm;
+    f[13] = ratio_f(esc, m);
     f[14] = flog(Pp);
     f[15] = 1.0f;
 }

@@ -1,4 +1,5 @@
 // Host side of the sznb C ABI: argument checks, workspace layout, launches.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -13,7 +14,10 @@ namespace sznb {
 __global__ void k_init(const CField *, int, GCtl *, uint64_t *, uint64_t);
 __global__ void k_range(const CField *, int, const uint64_t *, uint64_t);
 __global__ void k_params(const CField *);
-template <int E> __global__ void k_quant(const CField *, int, const uint64_t *, uint64_t, const uint32_t *);
+template <int E, bool kLearn>
+__global__ void k_quant(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, uint32_t,
+                        const uint32_t *, uint32_t *, const float *);
+__global__ void k_hmerge(const CField *, uint32_t, uint32_t, const uint32_t *, const uint32_t *);
 __global__ void k_huff(const CField *, int, uint8_t *, uint64_t);
 __global__ void k_books(const CField *);
 template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, uint64_t, GCtl *);
@@ -142,11 +146,15 @@ static bool mode_ok(uint32_t mode) {
 
 // ----------------------------------------------------------- compress plan
 
+constexpr uint64_t kMaxQuantWG = 4096;  // workgroups of the quantization kernel, at most
+
 struct CLayout {
-  uint64_t gctl, states, fields, fb0, blkstat, lbflag, perfield_base, hscratch, total;
+  uint64_t gctl, states, fields, fb0, blkstat, lbflag, perfield_base, hscratch, qmeta, slabs, total;
   std::vector<uint64_t> hist, enc, book, nblocks, gblock0, nhist;
   uint64_t total_blocks;
-  int nslots;
+  int nslots;         // Huffman workgroups: (field, predictor) pairs, at most 64
+  uint32_t qslots;    // histogram windows per quantization workgroup
+  uint64_t qmax;      // quantization workgroups the slabs are sized for
 };
 
 static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) {
@@ -177,8 +185,46 @@ static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) 
   }
   L.nslots = npairs < 64 ? (npairs > 0 ? npairs : 1) : 64;
   L.hscratch = o; o = al256(o + hscratch_bytes_host() * (uint64_t)L.nslots);
+  // quantization plan: per workgroup its first visit and first field, per
+  // field its first and last workgroup; one histogram slab per visit
+  L.qslots = 1;
+  for (int f = 0; f < nf; f++) L.qslots = std::max<uint32_t>(L.qslots, (uint32_t)L.nhist[f]);
+  L.qmax = std::max<uint64_t>(1, std::min<uint64_t>(kMaxQuantWG, L.total_blocks));
+  L.qmeta = o; o = al256(o + 4ull * (2 * L.qmax + 1 + 2ull * nf));
+  L.slabs = o; o = al256(o + 4ull * kWinWords * (L.qmax + (uint64_t)nf));
   L.total = o;
   return L;
+}
+
+// The quantization plan of a grid of G workgroups over the field table:
+// workgroup w takes blocks [w T / G, (w + 1) T / G).
+static void quant_plan(const CLayout &L, int nf, uint32_t G, std::vector<uint32_t> &meta) {
+  const uint64_t T = L.total_blocks;
+  meta.assign(2 * (size_t)G + 1 + 2 * (size_t)nf, 0u);
+  uint32_t *visit_base = meta.data(), *ffirst = visit_base + G + 1, *wf0 = ffirst + G, *wf1 = wf0 + nf;
+  auto field_of = [&](uint64_t g) {  // largest f with gblock0[f] <= g (fields without blocks skipped)
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (L.gblock0[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  for (int f = 0; f < nf; f++) { wf0[f] = 1; wf1[f] = 0; }
+  for (uint32_t w = 0; w < G; w++) {
+    const uint64_t gb = (uint64_t)w * T / G, ge = ((uint64_t)w + 1) * T / G;
+    uint32_t f0 = 0, f1 = 0;
+    if (ge > gb) {
+      f0 = (uint32_t)field_of(gb);
+      f1 = (uint32_t)field_of(ge - 1);
+      for (uint32_t f = f0; f <= f1; f++) {
+        if (wf0[f] > wf1[f]) wf0[f] = w;
+        wf1[f] = w;
+      }
+    }
+    ffirst[w] = f0;
+    visit_base[w + 1] = visit_base[w] + (ge > gb ? f1 - f0 + 1 : 0);
+  }
 }
 
 static uint64_t compress_bound_impl(uint64_t n, uint32_t mode) {
@@ -198,6 +244,10 @@ static uint64_t compress_min_cap_impl(uint64_t n, uint32_t mode) {
 }
 
 struct Launch {
+  int cus;
+  bool learned;   // some field uses the learned policy
+  uint32_t gq;    // quantization workgroups (the plan in the workspace is for this count)
+  const float *sel;  // selector parameters of the learned policy (device)
   int E;
   uint64_t total_blocks;
   int nf;
@@ -213,7 +263,15 @@ static void launch_quant_pack(bool quant, const Launch &P, hipStream_t s, int gr
   if (quant) {
     uint32_t *logt = nullptr;
     (void)hipGetSymbolAddress(reinterpret_cast<void **>(&logt), HIP_SYMBOL(g_logt));
-    SZNB_LAUNCH("k_quant", k_quant<E>, dim3(grid), dim3(kThreads), 0, s, F, P.nf, fb0, P.total_blocks, logt);
+    const size_t smem = (size_t)kWinWords * sizeof(uint32_t);
+    auto kern = P.learned ? k_quant<E, true> : k_quant<E, false>;
+    SZNB_LAUNCH("k_quant", kern, dim3(P.gq), dim3(kThreads), smem, s, F, P.nf, fb0, P.total_blocks, logt,
+                P.L.qslots, reinterpret_cast<const uint32_t *>(P.ws + P.L.qmeta),
+                reinterpret_cast<uint32_t *>(P.ws + P.L.slabs), P.sel);
+    SZNB_LAUNCH("k_hmerge", k_hmerge, dim3(qwin_of(P.L.qslots, 0).size / 256, P.L.qslots, P.nf), dim3(256), 0, s, F,
+                P.L.qslots, P.gq,
+                reinterpret_cast<const uint32_t *>(P.ws + P.L.qmeta),
+                reinterpret_cast<const uint32_t *>(P.ws + P.L.slabs));
   } else {
     SZNB_LAUNCH("k_pack", k_pack<E>, dim3(grid), dim3(kThreads), 0, s, F, P.nf, fb0, P.total_blocks,
                 reinterpret_cast<GCtl *>(P.ws + P.L.gctl));
@@ -228,6 +286,30 @@ static void launch_E(bool quant, const Launch &P, hipStream_t s, int grid) {
     case 32: launch_quant_pack<32>(quant, P, s, grid); break;
     default: launch_quant_pack<64>(quant, P, s, grid); break;
   }
+}
+
+// Workgroups of the quantization kernel: as many as stay resident together
+// (each takes a contiguous run of blocks), a multiple of the XCD count.
+template <int E>
+static int quant_occupancy(bool learned, size_t smem) {
+  int occ = 0;
+  auto kern = learned ? k_quant<E, true> : k_quant<E, false>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kThreads, smem) != hipSuccess || occ < 1) occ = 1;
+  return occ;
+}
+static uint32_t quant_grid(int E, bool learned, const CLayout &L, int cus) {
+  const size_t smem = (size_t)kWinWords * sizeof(uint32_t);
+  int occ = 1;
+  switch (E) {
+    case 4: occ = quant_occupancy<4>(learned, smem); break;
+    case 8: occ = quant_occupancy<8>(learned, smem); break;
+    case 16: occ = quant_occupancy<16>(learned, smem); break;
+    case 32: occ = quant_occupancy<32>(learned, smem); break;
+    default: occ = quant_occupancy<64>(learned, smem); break;
+  }
+  uint64_t g = std::min<uint64_t>({(uint64_t)cus * (uint64_t)occ, L.total_blocks, L.qmax});
+  if (g > 8) g &= ~uint64_t(7);
+  return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
 // waves per CU used for the persistent per-block kernels (tunable)
@@ -308,6 +390,13 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
     fb0[f] = L.gblock0[f];
   }
   fb0[nf] = L.total_blocks;
+  bool learned = false;
+  for (int f = 0; f < nf; f++) learned |= (mode[f] & 3u) == 3u;
+  const uint32_t gq = quant_grid((int)((1u << s0) / kThreads), learned, L, dv->cus);
+  std::vector<uint32_t> qmeta;
+  quant_plan(L, nf, gq, qmeta);
+  if (hipMemcpyAsync(ws + L.qmeta, qmeta.data(), 4 * qmeta.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return SZNB_EDEVICE;
   if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(CField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
     return SZNB_EDEVICE;
   if (hipMemcpyAsync(ws + L.fb0, fb0.data(), 8ull * (nf + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -315,6 +404,10 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
   // pageable source buffers must stay valid until the copies are consumed
   if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
   Launch P;
+  P.cus = dv->cus;
+  P.learned = learned;
+  P.gq = gq;
+  P.sel = dv->sel;
   P.E = (int)((1u << s0) / kThreads);
   P.total_blocks = L.total_blocks;
   P.nf = nf;
@@ -358,6 +451,10 @@ static int features_impl(int nf, const float *const *fields, const uint64_t *n, 
   DevInfo *dv;
   if ((rc = dev_init(&dv))) return rc;
   Launch P;
+  P.cus = dv->cus;
+  P.learned = false;
+  P.gq = 1;
+  P.sel = nullptr;
   P.E = (int)((1u << block_log2_of(mode[0])) / kThreads);
   P.total_blocks = L.total_blocks;
   P.nf = nf;

@@ -15,7 +15,6 @@
 
 namespace sznb {
 
-constexpr int kWin = 2048;  // LDS window of the code histogram around code 32768
 
 // ------------------------------------------------------------------ init
 
@@ -225,18 +224,12 @@ __device__ inline int32_t lattice_of(float x, float mn, double inv) {
   return (int32_t)floor(__dadd_rn(t, 0.5));
 }
 
-// Loads this thread's E contiguous values of the block, computes the lattice
-// index relative to the block anchor (d_j = p_j - p_0), and fetches the three
-// values that precede the thread's run (zero before the block start).
+// This thread's E contiguous values of a block (16-byte loads when the run
+// is whole; the tail of a ragged block reads as mn).
 template <int E>
-__device__ inline void load_block_d(const CField &c, const FState *st, uint64_t i0, uint32_t len,
-                                    int32_t (&d)[E], int32_t (&pv)[3], int32_t *s_tail, int32_t &p0_out,
-                                    int32_t *s_p0) {
+__device__ inline void load_raw(const float *x_block, uint32_t len, float mn, float (&v)[E]) {
   const int t = threadIdx.x;
-  const float mn = st->mn;
-  const double inv = st->inv;
-  const float *x = c.x + i0 + (uint64_t)t * E;
-  float v[E];
+  const float *x = x_block + (uint64_t)t * E;
   if ((uint32_t)(t + 1) * E <= len) {
 #pragma unroll
     for (int e = 0; e < E; e += 4) {
@@ -247,6 +240,17 @@ __device__ inline void load_block_d(const CField &c, const FState *st, uint64_t 
 #pragma unroll
     for (int e = 0; e < E; e++) v[e] = ((uint32_t)t * E + e < len) ? x[e] : mn;
   }
+}
+
+// Lattice index of this thread's values relative to the block anchor
+// (d_j = p_j - p_0), and the three values that precede the thread's run
+// (zero before the block start).
+template <int E>
+__device__ inline void block_d_from_raw(const float (&v)[E], const FState *st, int32_t (&d)[E], int32_t (&pv)[3],
+                                        int32_t *s_tail, int32_t &p0_out, int32_t *s_p0) {
+  const int t = threadIdx.x;
+  const float mn = st->mn;
+  const double inv = st->inv;
   int32_t p[E];
 #pragma unroll
   for (int e = 0; e < E; e++) p[e] = lattice_of(v[e], mn, inv);
@@ -262,6 +266,15 @@ __device__ inline void load_block_d(const CField &c, const FState *st, uint64_t 
   if (t == 0) { pv[0] = pv[1] = pv[2] = 0; }
   else { pv[0] = s_tail[3 * (t - 1)]; pv[1] = s_tail[3 * (t - 1) + 1]; pv[2] = s_tail[3 * (t - 1) + 2]; }
   p0_out = p0;
+}
+
+template <int E>
+__device__ inline void load_block_d(const CField &c, const FState *st, uint64_t i0, uint32_t len,
+                                    int32_t (&d)[E], int32_t (&pv)[3], int32_t *s_tail, int32_t &p0_out,
+                                    int32_t *s_p0) {
+  float v[E];
+  load_raw<E>(c.x + i0, len, st->mn, v);
+  block_d_from_raw<E>(v, st, d, pv, s_tail, p0_out, s_p0);
 }
 
 // residual of predictor k at element e given the run d[] and its three
@@ -327,15 +340,17 @@ __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3]
   __syncthreads();
 }
 
-// Selector features of one block (exact integer sums and counts of the
-// lattice values p and of their LV / LCF residuals Dp, D2p):
-//   0 sum p / (len P')   1 (max p - min p) / P'   2 F(sum|Dp|) - F(len)
-//   3 F(sum|D2p|) - F(len)   4 F(max|Dp|)   5 F(max|D2p|)   6 #(Dp=0)/len
-//   7 #(D2p=0)/len   8 #(|Dp|<=1)/len   9 #(|D2p|<=1)/len
-//   10 #(sign changes of Dp)/len   11 F(sum bitlen|Dp|) - F(len)
-//   12 F(sum bitlen|D2p|) - F(len)   13 #(|Dp|>=32768)/len   14 F(P')   15 1
+// Selector features of one block, read on every 4th position of the block
+// (exact integer sums and counts of the lattice values p and of their LV /
+// LCF residuals Dp, D2p over the sample J = {j : j = 0 mod 4}, m = |J|):
+//   0 sum p / (m P')   1 (max p - min p) / P'   2 F(sum|Dp|) - F(m)
+//   3 F(sum|D2p|) - F(m)   4 F(max|Dp|)   5 F(max|D2p|)   6 #(Dp=0)/m
+//   7 #(D2p=0)/m   8 #(|Dp|<=1)/m   9 #(|D2p|<=1)/m
+//   10 #(Dp_j Dp_{j-1} < 0)/m   11 F(sum bitlen|Dp|) - F(m)
+//   12 F(sum bitlen|D2p|) - F(m)   13 #(|Dp|>=32768)/m   14 F(P')   15 1
 // with P' = max(P, 1), F = flog_u64 and every ratio one fp64 division
 // rounded to float.  Leaves the 16 features in s_feat.
+constexpr int kFeatStride = 4;
 struct FeatRed {
   long long sd[kThreads / kWave];
   unsigned long long s1[kThreads / kWave], s2[kThreads / kWave];
@@ -366,11 +381,14 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
   unsigned long long s1 = 0, s2 = 0;
   int32_t dmx = INT32_MIN, dmn = INT32_MAX;
   uint32_t m1 = 0, m2 = 0, zz = 0, oo = 0, se = 0, b1 = 0, b2 = 0;
-  // Dp of the element before this thread's run (zero before the block)
-  int32_t prev = (int32_t)((uint32_t)pv[0] - (uint32_t)pv[1]);
 #pragma unroll
-  for (int e = 0; e < E; e++) {
-    const int32_t r1 = residual_at<E>(d, pv, e, 0), r2 = residual_at<E>(d, pv, e, 1);
+  for (int e = 0; e < E; e += kFeatStride) {
+    // Dp at e - 1 and at e, D2p at e (values before the block read as zero)
+    const int32_t dm1 = e >= 1 ? d[e - 1] : pv[0];
+    const int32_t dm2 = e >= 2 ? d[e - 2] : (e == 1 ? pv[0] : pv[1]);
+    const int32_t prev = (int32_t)((uint32_t)dm1 - (uint32_t)dm2);
+    const int32_t r1 = (int32_t)((uint32_t)d[e] - (uint32_t)dm1);
+    const int32_t r2 = (int32_t)((uint32_t)r1 - (uint32_t)prev);
     if ((uint32_t)t * E + e < len) {
       const uint32_t a1 = (uint32_t)(r1 < 0 ? -r1 : r1), a2 = (uint32_t)(r2 < 0 ? -r2 : r2);
       sd += d[e];
@@ -386,7 +404,6 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
       b1 += 32u - __clz(a1);
       b2 += 32u - __clz(a2);
     }
-    prev = r1;
   }
   sd = wave_sum(sd);
   s1 = wave_sum(s1);
@@ -405,7 +422,9 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
     r->zz[w] = zz; r->oo[w] = oo; r->se[w] = se; r->b1[w] = b1; r->b2[w] = b2;
   }
   __syncthreads();
-  if (t == 0) {
+  // thread k < 16 finishes feature k: one numerator / denominator pair and
+  // one kind of formula each, so that a single division is in flight
+  if (t < kNFeat) {
     for (int v = 1; v < kThreads / kWave; v++) {
       sd += r->sd[v]; s1 += r->s1[v]; s2 += r->s2[v];
       dmx = max(dmx, r->dmx[v]); dmn = min(dmn, r->dmn[v]);
@@ -413,34 +432,70 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
       zz += r->zz[v]; oo += r->oo[v]; se += r->se[v]; b1 += r->b1[v]; b2 += r->b2[v];
     }
     const uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
-    const long long sum_p = sd + (long long)len * (long long)p0;
-    auto ratio = [](uint64_t a, uint64_t b) { return __double2float_rn(__ddiv_rn((double)a, (double)b)); };
-    const float fl = flog_u64(len);
-    s_feat[0] = ratio((uint64_t)sum_p, (uint64_t)len * Pp);
-    s_feat[1] = ratio((uint64_t)((int64_t)dmx - (int64_t)dmn), Pp);
-    s_feat[2] = flog_u64(s1) - fl;
-    s_feat[3] = flog_u64(s2) - fl;
-    s_feat[4] = flog_u64(m1);
-    s_feat[5] = flog_u64(m2);
-    s_feat[6] = ratio(zz & 0xffffu, len);
-    s_feat[7] = ratio(zz >> 16, len);
-    s_feat[8] = ratio(oo & 0xffffu, len);
-    s_feat[9] = ratio(oo >> 16, len);
-    s_feat[10] = ratio(se & 0xffffu, len);
-    s_feat[11] = flog_u64(b1) - fl;
-    s_feat[12] = flog_u64(b2) - fl;
-    s_feat[13] = ratio(se >> 16, len);
-    s_feat[14] = flog_u64(Pp);
-    s_feat[15] = 1.0f;
+    const uint32_t m = (len + kFeatStride - 1) / kFeatStride;  // sampled positions
+    uint64_t a = 0, den = m;
+    int kind = 0;  // 0: a / den, 1: F(a) - F(m), 2: F(a), 3: one
+    switch (t) {
+      case 0: a = (uint64_t)(sd + (long long)m * (long long)p0); den = (uint64_t)m * Pp; break;
+      case 1: a = (uint64_t)((int64_t)dmx - (int64_t)dmn); den = Pp; break;
+      case 2: a = s1; kind = 1; break;
+      case 3: a = s2; kind = 1; break;
+      case 4: a = m1; kind = 2; break;
+      case 5: a = m2; kind = 2; break;
+      case 6: a = zz & 0xffffu; break;
+      case 7: a = zz >> 16; break;
+      case 8: a = oo & 0xffffu; break;
+      case 9: a = oo >> 16; break;
+      case 10: a = se & 0xffffu; break;
+      case 11: a = b1; kind = 1; break;
+      case 12: a = b2; kind = 1; break;
+      case 13: a = se >> 16; break;
+      case 14: a = Pp; kind = 2; break;
+      default: kind = 3; break;
+    }
+    float fv;
+    if (kind == 0) fv = __double2float_rn(__ddiv_rn((double)a, (double)den));
+    else if (kind == 1) fv = flog_u64(a) - flog_u64(m);
+    else if (kind == 2) fv = flog_u64(a);
+    else fv = 1.0f;
+    s_feat[t] = fv;
   }
   __syncthreads();
 }
 
-template <int E>
-__global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F, int nf,
+// Adds v (<= 64) to 16-bit counter idx16 of the LDS window; a counter that
+// wraps hands 65536 to its global histogram bin (and the carry it pushed
+// into its upper neighbour is taken back).
+__device__ inline void win_add(uint32_t *s_win, uint32_t idx16, uint32_t v, uint32_t *gbin) {
+  const uint32_t sh = (idx16 & 1u) << 4;
+  const uint32_t old = atomicAdd(&s_win[idx16 >> 1], v << sh);
+  if (((old >> sh) & 0xffffu) + v > 0xffffu) {
+    if (!sh) atomicSub(&s_win[idx16 >> 1], 0x10000u);
+    atomicAdd(gbin, 0x10000u);
+  }
+}
+
+// Each workgroup takes one contiguous run of blocks and counts codes in LDS
+// windows of 16-bit counters (qwin_of).  When it leaves a field it stores
+// the window words to its own slab: the visit (workgroup w, field f) owns
+// slab visit_base[w] + f - ffirst[w].  k_hmerge then adds the slabs of each
+// field into its histogram.  (Device-scope atomics are executed beyond the
+// XCD's L2, at the memory side, and are slow; only codes outside the window
+// and counter wraps take that path.)
+template <int E, bool kLearn>
+__global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField *__restrict__ F, int nf,
                                                     const uint64_t *__restrict__ fb0, uint64_t total,
-                                                    const uint32_t *__restrict__ logt) {
+                                                    const uint32_t *__restrict__ logt, uint32_t nslots,
+                                                    const uint32_t *__restrict__ qmeta, uint32_t *__restrict__ slabs,
+                                                    const float *__restrict__ sel) {
   constexpr int S = E * kThreads;
+  extern __shared__ uint32_t s_win[];
+  // the selector's parameters, staged once per workgroup (learned policy)
+  __shared__ float s_mlp[kLearn ? kMlpParams : 1];
+  if (kLearn) {
+    for (int i = threadIdx.x; i < kMlpParams; i += kThreads) s_mlp[i] = sel[i];
+    __syncthreads();
+  }
   __shared__ int32_t s_tail[3 * kThreads];
   __shared__ uint32_t s_cls[3 * kNClass];
   __shared__ uint32_t s_extra[3];
@@ -449,25 +504,36 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
   __shared__ int s_pred, s_fb;
   __shared__ FeatRed s_red;
   __shared__ float s_feat[kNFeat];
-  __shared__ uint32_t s_win[3 * kWin];
   const int t = threadIdx.x;
-  const uint32_t wbase = kRadius - kWin / 2;
   int cur = -1;
 
   auto flush = [&](int f) {
     __syncthreads();
     if (f >= 0) {
-      const CField &c = F[f];
-      for (uint32_t i = t; i < c.nhist * kWin; i += kThreads) {
-        uint32_t v = s_win[i];
-        if (v) atomicAdd(&c.hist[(i / kWin) * kNSyms + wbase + (i % kWin)], v);
-      }
+      const uint32_t *visit_base = qmeta, *ffirst = qmeta + gridDim.x + 1;
+      uint32_t *slab = slabs + (uint64_t)(visit_base[blockIdx.x] + (uint32_t)f - ffirst[blockIdx.x]) * kWinWords;
+      for (uint32_t i = t; i < (uint32_t)kWinWords; i += kThreads) slab[i] = s_win[i];
     }
-    for (uint32_t i = t; i < 3 * kWin; i += kThreads) s_win[i] = 0;
+    for (uint32_t i = t; i < (uint32_t)kWinWords; i += kThreads) s_win[i] = 0;
     __syncthreads();
   };
 
-  for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
+  const uint64_t g_begin = (uint64_t)blockIdx.x * total / gridDim.x;
+  const uint64_t g_end = ((uint64_t)blockIdx.x + 1) * total / gridDim.x;
+  // the values of block g + 1 are loaded while block g is processed
+  auto fetch = [&](uint64_t g, float (&v)[E]) {
+    const int f = find_field(fb0, nf, g);
+    const CField &c = F[f];
+    const uint64_t i0 = (g - c.gblock0) * S;
+    load_raw<E>(c.x + i0, (uint32_t)min((uint64_t)S, c.n - i0), c.st->mn, v);
+  };
+  float vn[E];
+  if (g_begin < g_end) fetch(g_begin, vn);
+  for (uint64_t g = g_begin; g < g_end; g++) {
+    float v[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) v[e] = vn[e];
+    if (g + 1 < g_end) fetch(g + 1, vn);
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
     const FState *st = c.st;
@@ -477,16 +543,16 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
     int32_t d[E], pv[3], p0;
-    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
+    block_d_from_raw<E>(v, st, d, pv, s_tail, p0, &s_p0);
 
     int pred = (int)c.policy;
     if (c.policy >= 2) {
       bool trial = true;
-      if (c.policy == 3) {
+      if (kLearn && c.policy == 3) {
         block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
         if (t < kWave) {
           float margin, z[3];
-          const int top = mlp_select_wave(c.sel, s_feat, margin, z);
+          const int top = mlp_select_wave(s_mlp, s_feat, margin, z);
           if (t == 0) {
             s_pred = top;
             s_fb = !(margin >= c.tau);
@@ -504,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
 
     // code histogram of the chosen predictor
     const int slot = c.policy >= 2 ? pred : 0;
-    uint32_t *win = s_win + slot * kWin;
+    const QWin qw = qwin_of(nslots, (uint32_t)slot);
     uint32_t *gh = c.hist + (uint64_t)slot * kNSyms;
 #pragma unroll
     for (int e = 0; e < E; e++) {
@@ -513,15 +579,39 @@ __global__ __launch_bounds__(kThreads) void k_quant(const CField *__restrict__ F
       uint32_t q = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
       // the zero residual is aggregated per wave (it dominates smooth fields)
       const uint64_t zmask = __ballot(valid && q == (uint32_t)kRadius);
-      if ((t & (kWave - 1)) == 0 && zmask) atomicAdd(&win[kRadius - wbase], (uint32_t)__popcll(zmask));
+      if ((t & (kWave - 1)) == 0 && zmask)
+        win_add(s_win, qw.off + qw.size / 2, (uint32_t)__popcll(zmask), &gh[kRadius]);
       if (valid && q != (uint32_t)kRadius) {
-        if (q - wbase < (uint32_t)kWin) atomicAdd(&win[q - wbase], 1u);
+        if (q - qw.base < qw.size) win_add(s_win, qw.off + (q - qw.base), 1u, &gh[q]);
         else atomicAdd(&gh[q], 1u);
       }
     }
     __syncthreads();
   }
   flush(cur);
+}
+
+// Window part of each (field, predictor) code histogram: adds the 16-bit
+// counters of the slabs of every workgroup that visited the field (see
+// k_quant) to the wrap carries and out-of-window counts already there.
+// Grid: (largest window / 256, nslots, nf).
+__global__ __launch_bounds__(256) void k_hmerge(const CField *__restrict__ F, uint32_t nslots, uint32_t G,
+                                                const uint32_t *__restrict__ qmeta,
+                                                const uint32_t *__restrict__ slabs) {
+  const int f = blockIdx.z;
+  const uint32_t slot = blockIdx.y;
+  const CField &c = F[f];
+  if (slot >= c.nhist || c.st->status != 0 || c.st->is_const) return;
+  const QWin qw = qwin_of(nslots, slot);
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= qw.size) return;
+  const uint32_t *visit_base = qmeta, *ffirst = qmeta + G + 1, *wf0 = qmeta + 2 * G + 1;
+  const uint32_t *wf1 = wf0 + gridDim.z;
+  const uint32_t k = qw.off + i, sh = (k & 1u) << 4;
+  uint32_t v = 0;
+  for (uint32_t w = wf0[f]; w <= wf1[f] && w < G; w++)
+    v += (slabs[(uint64_t)(visit_base[w] + (uint32_t)f - ffirst[w]) * kWinWords + (k >> 1)] >> sh) & 0xffffu;
+  c.hist[(uint64_t)slot * kNSyms + qw.base + i] += v;
 }
 
 // Training data of the selector: features, the three trial costs and the
@@ -1141,7 +1231,12 @@ __global__ void k_final(const CField *__restrict__ F, int nf) {
 
 // explicit instantiations (block sizes 1K..16K)
 #define SZNB_INST(E)                                                                                        \
-  template __global__ void k_quant<E>(const CField *, int, const uint64_t *, uint64_t, const uint32_t *); \
+  template __global__ void k_quant<E, false>(const CField *, int, const uint64_t *, uint64_t,              \
+                                             const uint32_t *, uint32_t, const uint32_t *, uint32_t *,      \
+                                             const float *);                                                \
+  template __global__ void k_quant<E, true>(const CField *, int, const uint64_t *, uint64_t,               \
+                                            const uint32_t *, uint32_t, const uint32_t *, uint32_t *,       \
+                                            const float *);                                                 \
   template __global__ void k_features<E>(const CField *, int, const uint64_t *, uint64_t, const uint32_t *,  \
                                          float *, uint64_t *, uint8_t *);                                    \
   template __global__ void k_pack<E>(const CField *, int, const uint64_t *, uint64_t, GCtl *);

@@ -17,6 +17,21 @@ constexpr int kLutBits = 12;         // first-level decode table
 constexpr int kNClass = 33;          // residual classes of the block-cost estimate
 constexpr int kThreads = 256;        // workgroup size of the per-block kernels
 constexpr int kWave = 64;
+// LDS windows of the code histograms around code 32768: 16-bit counters,
+// kWinWords 32-bit words per quantization workgroup.  One predictor slot
+// takes all 12288 counters; three slots take 8192 (LV) + 2048 + 2048.
+constexpr int kWinWords = 6144;
+struct QWin {
+  uint32_t base, size, off;  // first code, number of codes, first counter
+};
+__host__ __device__ inline QWin qwin_of(uint32_t nslots, uint32_t slot) {
+  QWin w;
+  if (nslots <= 1) { w.size = 2 * kWinWords; w.off = 0; }
+  else if (slot == 0) { w.size = 8192; w.off = 0; }
+  else { w.size = 2048; w.off = 8192 + 2048 * (slot - 1); }
+  w.base = 32768u - w.size / 2;
+  return w;
+}
 
 // header byte offsets
 enum : int {
@@ -196,13 +211,13 @@ __device__ inline int mlp_select_wave(const float *__restrict__ w, const float *
   for (int k = 0; k < kNFeat; k++) acc = __builtin_fmaf(w[kW1 + 16 * j + k], bf16_round(feat[k]), acc);
   const float h1 = bf16_round(acc > 0.0f ? acc : 0.0f);
   acc = w[kB2 + j];
-#pragma unroll
+#pragma unroll 8
   for (int k = 0; k < 32; k++)
     acc = __builtin_fmaf(w[kW2 + 32 * j + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), k)), acc);
   const float h2 = bf16_round(acc > 0.0f ? acc : 0.0f);
   const int jj = j < 3 ? j : 0;
   acc = w[kB3 + jj];
-#pragma unroll
+#pragma unroll 8
   for (int k = 0; k < 32; k++)
     acc = __builtin_fmaf(w[kW3 + 32 * jj + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h2), k)), acc);
   float z[3];

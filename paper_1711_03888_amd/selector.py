@@ -7,7 +7,7 @@ cosmology generators; features, trial costs and labels come from the
 library's feature kernel, the gradient and the Adam step from its training
 kernels.  Host code only shuffles, standardises and slices the data set.
 
-  python -m paper_1711_03888_amd.selector OUT.json [--blocks N] [--steps K]
+  python -m paper_1711_03888_amd.selector OUT.json [--data nbody|md] [--steps K]
 
 writes the parameters (feature standardisation folded into the first
 layer), the fallback threshold tau and the training record.
@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import os
 import sys
 import time
 
@@ -26,9 +27,9 @@ from . import datagen
 
 FORMAT_VERSION = 1
 # the feature definition the parameters are trained for (see sznb.h)
-FEATURE_SPEC = ("sum p/(len P'); (max p-min p)/P'; F(sum|Dp|)-F(len); F(sum|D2p|)-F(len); F(max|Dp|); "
-                "F(max|D2p|); #(Dp=0)/len; #(D2p=0)/len; #(|Dp|<=1)/len; #(|D2p|<=1)/len; #signchanges(Dp)/len; "
-                "F(sum bitlen|Dp|)-F(len); F(sum bitlen|D2p|)-F(len); #(|Dp|>=32768)/len; F(P'); 1")
+FEATURE_SPEC = ("sample j=0 mod 4, m positions: sum p/(m P'); (max p-min p)/P'; F(sum|Dp|)-F(m); "
+                "F(sum|D2p|)-F(m); F(max|Dp|); F(max|D2p|); #(Dp=0)/m; #(D2p=0)/m; #(|Dp|<=1)/m; #(|D2p|<=1)/m; "
+                "#(Dp_j Dp_j-1<0)/m; F(sum bitlen|Dp|)-F(m); F(sum bitlen|D2p|)-F(m); #(|Dp|>=32768)/m; F(P'); 1")
 FEATURE_HASH = hashlib.sha256(FEATURE_SPEC.encode()).hexdigest()[:16]
 EBS = (1e-3, 1e-4, 1e-5)
 
@@ -56,6 +57,17 @@ def generate_fields(n_walk: int, n_cosmo: int, seed: int, walk_n=1 << 20, cosmo_
         snap = datagen.cosmology(cosmo_n, seed=seed * 1000 + 500 + i, n_halos=halos)
         for name in datagen.FIELD_NAMES:
             out.append((snap[name], float(rng.choice(EBS))))
+    return out
+
+
+def generate_md_fields(n_snap: int, seed: int, cells=(32, 32, 64)):
+    """(field, eb_rel) pairs of FCC snapshots (the three coordinates)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_snap):
+        snap = datagen.md_lattice(cells=cells, seed=seed * 1000 + i)
+        for name in datagen.FIELD_NAMES[:3]:
+            out.append((snap[name], float(rng.choice(EBS[:2]))))
     return out
 
 
@@ -98,7 +110,7 @@ def choose_tau(margin, choice, cost, label, budget=0.002):
     # trust the k most confident blocks, k the longest prefix within budget
     k = int(np.argmin(ok)) if not ok.all() else len(ok)
     if k == len(ok):
-        return float(max(0.0, margin.min()))
+        return 0.0  # every block may be trusted: fall back on exact ties only
     return float(margin[order[k]]) + 1e-6
 
 
@@ -155,6 +167,10 @@ def save(path, params, tau, record):
                    "params": [float(v) for v in params], "record": record}, fh, indent=1)
 
 
+SELECTORS = {name: os.path.join(os.path.dirname(os.path.abspath(__file__)), "selectors", name + ".json")
+             for name in ("nbody", "md")}
+
+
 def load(path):
     with open(path) as fh:
         d = json.load(fh)
@@ -171,13 +187,19 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=100)
+    ap.add_argument("--data", choices=["nbody", "md"], default="nbody",
+                    help="random-walk and cosmology fields, or FCC coordinate fields")
+    ap.add_argument("--md-snapshots", type=int, default=48)
     args = ap.parse_args(argv)
     import torch
 
     from . import sznb
     dev = torch.device("cuda:0")
     t0 = time.time()
-    fields = generate_fields(args.walk_fields, args.cosmo_snapshots, args.seed)
+    if args.data == "md":
+        fields = generate_md_fields(args.md_snapshots, args.seed)
+    else:
+        fields = generate_fields(args.walk_fields, args.cosmo_snapshots, args.seed)
     mode = sznb.PRED_BESTFIT | sznb.EB_REL
     feat, cost, label = block_data(fields, mode, dev)
     print("blocks %d, labels LV/LCF/QCF %s, %.1fs" % (len(label), np.bincount(label, minlength=3).tolist(),
@@ -194,7 +216,9 @@ def main(argv=None):
     record = {"blocks": int(len(label)), "label_histogram": np.bincount(label, minlength=3).tolist(),
               "train_blocks": int(len(tr)), "heldout_blocks": int(n_val), "heldout_accuracy": acc,
               "heldout_fallback_rate": fb, "loss_curve": curve, "steps": args.steps, "batch": args.batch,
-              "seed": args.seed, "walk_fields": args.walk_fields, "cosmo_snapshots": args.cosmo_snapshots}
+              "seed": args.seed, "data": args.data, "walk_fields": args.walk_fields,
+              "cosmo_snapshots": args.cosmo_snapshots, "md_snapshots": args.md_snapshots,
+              "train_seconds": round(time.time() - t0, 1)}
     save(args.out, params, tau, record)
     print(json.dumps({k: v for k, v in record.items() if k != "loss_curve"}), "tau", tau, flush=True)
 

@@ -17,11 +17,12 @@ from paper_1711_03888_amd import datagen
 
 
 def test_flog_powers_of_two():
-    # F(2^k) = k + 1 exactly: a block whose sum |Dp| is 2^k
+    # F(2^k) = k + 1 exactly: a block whose sampled sum |Dp| is 2^k (samples
+    # at positions 0 and 4, m = 2)
     for k in range(0, 20):
-        q = np.array([0, 2 ** k], np.int32)
+        q = np.array([0, 0, 0, 0, 2 ** k], np.int32)
         f = oracle.features(q, 1024, 2 ** 27)[0]
-        assert f[2] == float(k + 1) - 2.0  # F(sum|Dp|) - F(len = 2)
+        assert f[2] == float(k + 1) - 2.0  # F(sum|Dp|) - F(m = 2)
 
 
 def test_features_constant_block():
@@ -30,7 +31,7 @@ def test_features_constant_block():
     assert f[0] == np.float32(777 / 1000)
     assert f[1] == 0
     assert f[4] == 0 and f[5] == 0  # F(0) = 0
-    assert f[6] == 1 and f[7] == 1 and f[8] == 1 and f[9] == 1
+    assert f[6] == 1 and f[7] == 1 and f[8] == 1 and f[9] == 1  # of m = 1024 samples
     assert f[10] == 0 and f[13] == 0
     assert f[14] == np.float32(10 + 0xf4 / 256)  # 1000 = 0b1111101000
     assert f[15] == 1
@@ -38,25 +39,30 @@ def test_features_constant_block():
 
 def test_features_ramp_and_zigzag():
     n, c = 4096, 5
+    m = n // 4  # sampled positions 0, 4, 8, ...
     ramp = (100 + c * np.arange(n)).astype(np.int32)
     f = oracle.features(ramp, n, 1 << 20)[0]
-    # Dp = (0, c, c, ...), D2p = (0, c, 0, 0, ...)
-    assert f[6] == np.float32(1 / n) and f[7] == np.float32((n - 1) / n)
-    assert f[4] == 3.25 and f[5] == 3.25  # F(5) = 3 + 0b01/4 = 3.25
+    # Dp = (0, c, c, ...), D2p = (0, c, 0, 0, ...): on the sample, Dp = 0
+    # only at 0 and D2p = 0 everywhere
+    assert f[6] == np.float32(1 / m) and f[7] == 1.0
+    assert f[4] == 3.25 and f[5] == 0.0  # F(5) = 3 + 0b01/4 = 3.25
     assert f[10] == 0
     zig = (100 + c * (np.arange(n) % 2)).astype(np.int32)
     f = oracle.features(zig, n, 1 << 20)[0]
-    # Dp = (0, c, -c, c, ...): a sign change at every j >= 2
-    assert f[10] == np.float32((n - 2) / n)
-    assert f[8] == np.float32(1 / n)
+    # Dp = (0, c, -c, c, ...): at every sampled j >= 4, Dp_j = -c after +c
+    assert f[10] == np.float32((m - 1) / m)
+    assert f[8] == np.float32(1 / m)
 
 
 def _features_numpy(q, P):
     q = q.astype(np.int64)
-    n = q.size
     d = q - q[0]
-    dp = np.diff(np.concatenate([[0], d]))
-    d2 = np.diff(np.concatenate([[0], dp]))
+    dp_all = np.diff(np.concatenate([[0], d]))
+    d2 = np.diff(np.concatenate([[0], dp_all]))[::4]
+    prev = np.concatenate([[0], dp_all])[:-1][::4]  # Dp at j - 1
+    dp = dp_all[::4]
+    q = q[::4]
+    n = q.size  # m, the sampled positions
     a1, a2 = np.abs(dp), np.abs(d2)
 
     def F(v):
@@ -71,7 +77,7 @@ def _features_numpy(q, P):
         return np.float32(np.float64(a) / np.float64(b))
 
     Pp = max(int(P), 1)
-    sc = int(np.sum((dp[1:] > 0) & (dp[:-1] < 0)) + np.sum((dp[1:] < 0) & (dp[:-1] > 0)))
+    sc = int(np.sum((dp > 0) & (prev < 0)) + np.sum((dp < 0) & (prev > 0)))
     bl1 = int(sum(int(v).bit_length() for v in a1))
     bl2 = int(sum(int(v).bit_length() for v in a2))
     fl = F(n)
