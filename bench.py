@@ -135,6 +135,132 @@ def learned_section(fields, eb, block_log2, steps, bestfit_ms, bestfit_quant_ms,
             "training": {k: rec.get(k) for k in ("blocks", "label_histogram", "heldout_accuracy", "data")}}
 
 
+def _gbps(nbytes, ms):
+    return round(nbytes / (ms * 1e-3) / 1e9, 2)
+
+
+def rebase(w):
+    """A slice of a long random walk restarted at zero and wrapped into
+    [0, 256), as a fresh walk of that length would be."""
+    import torch
+    return torch.remainder(w - w[0], 256.0).contiguous()
+
+
+def config1_steady(dev, walk, reps):
+    """256 distinct random-walk fields of 2^20 values (1 GiB), LV, one
+    graph-captured batched compression and one batched decompression; HBM
+    fraction of each on algorithmic bytes."""
+    import torch
+
+    from paper_1711_03888_amd import sznb
+    n, nf = 1 << 20, 256
+    fields = [rebase(walk[i * n:(i + 1) * n]) for i in range(nf)]
+    mode = sznb.PRED_LV | sznb.EB_REL
+    plan = sznb.CompressPlan(fields, 1e-4, mode)
+    side = torch.cuda.Stream()
+    plan.capture(side)
+    plan.launch(side)
+    side.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(side)
+    for _ in range(reps):
+        plan.launch(side)
+    b.record(side)
+    side.synchronize()
+    c_ms = a.elapsed_time(b) / reps
+    first, st = sznb.read_status(plan.ws, nf)
+    assert first == sznb.OK, st
+    streams = plan.streams()
+    comp = sum(s.numel() for s in streams)
+    recon = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(nf)]
+    wsd = sznb.workspace(sznb.decompress_workspace_bytes([n] * nf), dev)
+    sznb.decompress_batch_async(streams, [n] * nf, outs=recon, ws=wsd)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        sznb.decompress_batch_async(streams, [n] * nf, outs=recon, ws=wsd)
+    b.record()
+    torch.cuda.synchronize()
+    d_ms = a.elapsed_time(b) / reps
+    for x, y, o in zip(fields[:4], recon[:4], streams[:4]):
+        eb_abs = sznb.stream_info(bytes(o[:128].cpu().numpy()))["eb_abs"]
+        assert (x.double() - y.double()).abs().max().item() <= eb_abs
+    raw = 4.0 * n * nf
+    plan.close()
+    return {"workload": "256 random-walk fields x 2^20 float32 (1 GiB), LV, eb_rel 1e-4",
+            "ratio": round(raw / comp, 3),
+            "compress_GBps": _gbps(raw, c_ms), "decompress_GBps": _gbps(raw, d_ms),
+            "compress_hbm_frac": round((raw + comp) / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "decompress_hbm_frac": round((raw + comp) / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4)}
+
+
+def batched_512(dev, walk, cosmo, reps):
+    """512 uneven fields (sizes log-uniform in [64K, 16M], eb per field from
+    {1e-3, 1e-4, 1e-5}): even fields are slices of a long random walk, odd
+    fields slices of the cosmology snapshot; best-fit; autotuned block size
+    and grid width; one graph-captured launch against per-field launches."""
+    import numpy as np
+    import torch
+
+    from paper_1711_03888_amd import datagen, sznb
+    specs = datagen.batch_spec()
+    rng = np.random.default_rng(4)
+    fields, ebs = [], []
+    for sp in specs:
+        n = sp["n"]
+        src = walk if sp["kind"] == "walk" else cosmo[sp["field"]]
+        off = int(rng.integers(0, (src.numel() - n) // 4 + 1)) * 4
+        fields.append(rebase(src[off:off + n]) if sp["kind"] == "walk" else src[off:off + n])
+        ebs.append(sp["eb_rel"])
+    raw = 4.0 * sum(f.numel() for f in fields)
+    policy = sznb.PRED_BESTFIT | sznb.EB_REL
+    t0 = time.perf_counter()
+    mode, wg = sznb.autotune(fields, ebs, policy)
+    tune_s = time.perf_counter() - t0
+    sznb.set_workgroups_per_cu(wg)
+    try:
+        plan = sznb.CompressPlan(fields, ebs, mode)
+        side = torch.cuda.Stream()
+        plan.capture(side)
+        plan.launch(side)
+        side.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(side)
+        for _ in range(reps):
+            plan.launch(side)
+        b.record(side)
+        side.synchronize()
+        g_ms = a.elapsed_time(b) / reps
+        first, st = sznb.read_status(plan.ws, len(fields))
+        assert first == sznb.OK, st
+        comp = sum(s.numel() for s in plan.streams())
+        plan.close()
+        # the same fields, one compression call (launch sequence) per field
+        caps = [sznb.compress_bound(f.numel(), mode) for f in fields]
+        outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+        ws = sznb.workspace(max(sznb.compress_workspace_bytes([f.numel()], [mode]) for f in fields), dev)
+        lens = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def per_field():
+            for f, e, c, o in zip(fields, ebs, caps, outs):
+                sznb.compress_batch_async([f], e, mode, caps=[c], outs=[o], ws=ws, lens=lens)
+        per_field()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        per_field()
+        torch.cuda.synchronize()
+        p_ms = (time.perf_counter() - t1) * 1e3
+    finally:
+        sznb.set_workgroups_per_cu(8)
+    return {"workload": "512 fields, %.2f GB, sizes log-uniform in [64K, 16M], eb_rel from {1e-3, 1e-4, 1e-5}, "
+                        "best-fit" % (raw / 1e9),
+            "autotuned": {"block": 1 << ((mode >> 8) & 15), "workgroups_per_cu": wg, "seconds": round(tune_s, 2)},
+            "ratio": round(raw / comp, 3), "graph_compress_GBps": _gbps(raw, g_ms),
+            "per_field_compress_GBps": _gbps(raw, p_ms), "speedup": round(p_ms / g_ms, 2),
+            "graph_ms": round(g_ms, 3), "per_field_ms": round(p_ms, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-md", action="store_true", help="skip the MD-mode measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector measurement")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the steady-state 256 x 1M and the 512-field batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
@@ -261,6 +389,12 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(kern.items())},
     }
+
+    if not args.no_batch:
+        walk = torch.from_numpy(datagen.random_walk(1 << 28, seed=7)).to(dev)
+        out["config1_steady"] = config1_steady(dev, walk, max(3, args.steps))
+        out["batched_512"] = batched_512(dev, walk, fields, max(2, args.steps // 2))
+        del walk
 
     if not args.no_learned and args.policy == "bestfit":
         out["learned_selector"] = learned_section(fields, args.eb, args.block_log2, args.steps, c_ms,

@@ -111,6 +111,41 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
 
 const char *sznb_strerror(int status);
 
+/* ---- plans: many fields, one launch sequence, optionally one HIP graph
+ * sznb_compress_plan validates the field table (as sznb_compress_batch),
+ * writes its descriptors into d_ws and waits for that upload; the plan keeps
+ * the pointers, so inputs may change in place between launches, and d_ws and
+ * the outputs must outlive it.  sznb_plan_launch enqueues the compression
+ * kernels only (no host synchronisation, no memory-set nodes), so it can run
+ * under stream capture; sznb_plan_capture records it once into a HIP graph
+ * owned by the plan (stream: a non-default stream), after which
+ * sznb_plan_launch replays that graph.  Results are read as after
+ * sznb_compress_batch (sznb_read_status, d_lens). */
+typedef struct sznb_plan_s *sznb_plan;
+int sznb_compress_plan(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                       const uint32_t *h_mode, void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
+                       void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *plan_out);
+int sznb_plan_capture(sznb_plan plan, hipStream_t stream);
+int sznb_plan_launch(sznb_plan plan, hipStream_t stream);
+void sznb_plan_destroy(sznb_plan plan);
+
+/* Width of the persistent grids (range and pack kernels) in workgroups of
+ * 256 threads per compute unit, 1..16 (default 8); process-wide. */
+int sznb_set_workgroups_per_cu(int wg);
+int sznb_get_workgroups_per_cu(void);
+
+/* Autotuner: times compression of the given fields for block sizes 2^10 ..
+ * 2^14 and 2, 4, 8, 16 workgroups per CU, keeps the candidates whose total
+ * stream size is within 1 % of the smallest and returns the fastest as a mode
+ * (policy_mode | SZNB_BLOCK_LOG2(b)) and a width for
+ * sznb_set_workgroups_per_cu.  policy_mode holds only predictor and
+ * SZNB_EB_REL bits.  With cache_path, a line keyed by (GPU architecture,
+ * log2 of the total value count, log2 of the field count, policy) is looked
+ * up first and appended after a tuning run.  Allocates its own scratch. */
+int sznb_autotune(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                  uint32_t policy_mode, const char *cache_path, uint32_t *h_best_mode, int *h_best_wg,
+                  hipStream_t stream);
+
 /* ---- learned predictor selector (SZNB_PRED_LEARNED)
  * Not part of the paper, whose methods fix one predictor each (Sec. 5.1): a
  * small network 16 -> 32 -> 32 -> 3 (ReLU) reads 16 statistics of a block's

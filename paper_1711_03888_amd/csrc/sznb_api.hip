@@ -3,7 +3,10 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <cstdio>
 #include <mutex>
+#include <new>
+#include <string>
 #include <vector>
 
 #include "sznb_internal.h"
@@ -81,6 +84,8 @@ struct ProfScope {
   hipStream_t s;
   ProfScope(const char *n, hipStream_t st) : name(n), s(st) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     hipEvent_t a = prof_event();
     b = prof_event();
     if (!a || !b) { b = nullptr; return; }
@@ -336,12 +341,13 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
-static int compress_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
-                         const uint32_t *mode, void *const *outs, const uint64_t *caps, uint64_t *d_lens,
-                         bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream,
-                         bool params_only = false) {
+// Validates a field table, writes its descriptors and quantization plan
+// into the workspace (waits for the upload) and fills the launch record.
+static int compress_prepare(int nf, const float *const *fields, const uint64_t *n, const double *eb,
+                            const uint32_t *mode, void *const *outs, const uint64_t *caps, uint64_t *d_lens,
+                            bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream, Launch &P,
+                            DevInfo *&dv) {
   if (nf <= 0 || !d_ws) return SZNB_EINVAL;
-  DevInfo *dv;
   int rc = dev_init(&dv);
   if (rc) return rc;
   uint32_t s0 = 0;
@@ -403,7 +409,6 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
     return SZNB_EDEVICE;
   // pageable source buffers must stay valid until the copies are consumed
   if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
-  Launch P;
   P.cus = dv->cus;
   P.learned = learned;
   P.gq = gq;
@@ -414,7 +419,199 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
   P.nslots = L.nslots;
   P.ws = ws;
   P.L = L;
+  return SZNB_OK;
+}
+
+static int compress_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
+                         const uint32_t *mode, void *const *outs, const uint64_t *caps, uint64_t *d_lens,
+                         bool lens_is_array, void *d_ws, uint64_t ws_bytes, hipStream_t stream,
+                         bool params_only = false) {
+  Launch P;
+  DevInfo *dv = nullptr;
+  int rc = compress_prepare(nf, fields, n, eb, mode, outs, caps, d_lens, lens_is_array, d_ws, ws_bytes, stream, P, dv);
+  if (rc) return rc;
   return compress_run(P, stream, dv, params_only);
+}
+
+// ------------------------------------------------- plans and HIP graphs
+
+}  // namespace sznb
+
+struct sznb_plan_s {
+  sznb::Launch P;
+  sznb::DevInfo *dv = nullptr;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace sznb {
+
+static int plan_create(int nf, const float *const *fields, const uint64_t *n, const double *eb, const uint32_t *mode,
+                       void *const *outs, const uint64_t *caps, uint64_t *d_lens, void *d_ws, uint64_t ws_bytes,
+                       hipStream_t stream, sznb_plan *out) {
+  if (!out) return SZNB_EINVAL;
+  *out = nullptr;
+  sznb_plan p = new (std::nothrow) sznb_plan_s;
+  if (!p) return SZNB_EDEVICE;
+  int rc = compress_prepare(nf, fields, n, eb, mode, outs, caps, d_lens, true, d_ws, ws_bytes, stream, p->P, p->dv);
+  if (rc == SZNB_OK && hipGetDevice(&p->device) != hipSuccess) rc = SZNB_EDEVICE;
+  if (rc) { delete p; return rc; }
+  *out = p;
+  return SZNB_OK;
+}
+
+static int plan_graph(sznb_plan p, hipStream_t stream) {
+  if (!p) return SZNB_EINVAL;
+  if (p->exec) return SZNB_OK;
+  if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SZNB_EDEVICE;
+  const int rc = compress_run(p->P, stream, p->dv);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(stream, &g);
+  if (rc || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : SZNB_EDEVICE;
+  }
+  if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    p->exec = nullptr;
+    return SZNB_EDEVICE;
+  }
+  p->graph = g;
+  return SZNB_OK;
+}
+
+static int plan_run(sznb_plan p, hipStream_t stream) {
+  if (!p) return SZNB_EINVAL;
+  if (p->exec) return hipGraphLaunch(p->exec, stream) == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+  return compress_run(p->P, stream, p->dv);
+}
+
+static void plan_destroy(sznb_plan p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  delete p;
+}
+
+// ------------------------------------------------------------- autotuner
+//
+// Times the compression of a field table for every block size 2^10..2^14
+// and every persistent-grid width of 2, 4, 8, 16 workgroups per CU (kernel
+// time, HIP events, best of three after a warm-up), keeps the candidates
+// whose streams are within 1 % of the smallest, and picks the fastest.
+// Results are cached in a text file, one line per key:
+//   <arch>|<log2 total values>|<fields>|<policy bits> <block log2> <wg per CU> <ms>
+
+static std::string tune_key(int nf, const uint64_t *n, uint32_t policy_mode) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t p;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&p, dev) == hipSuccess) arch = p.gcnArchName;
+  for (char &ch : arch) if (ch == ' ' || ch == '|') ch = '_';
+  uint64_t tot = 0;
+  for (int f = 0; f < nf; f++) tot += n[f];
+  int cls = 0;
+  while ((tot >> cls) > 1) cls++;
+  int fcls = 0;
+  while ((1 << fcls) < nf) fcls++;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|%d|%d|%u", arch.c_str(), cls, fcls, policy_mode & 0x13u);
+  return buf;
+}
+
+static int autotune_impl(int nf, const float *const *fields, const uint64_t *n, const double *eb,
+                         uint32_t policy_mode, const char *cache_path, uint32_t *best_mode, int *best_wg,
+                         hipStream_t stream) {
+  if (nf <= 0 || !best_mode || !best_wg || (policy_mode & ~0x13u)) return SZNB_EINVAL;
+  DevInfo *dv;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  const std::string key = tune_key(nf, n, policy_mode);
+  if (cache_path) {
+    if (FILE *fp = std::fopen(cache_path, "r")) {
+      char k[256];
+      int bl = 0, wg = 0;
+      double ms = 0;
+      bool hit = false;
+      while (std::fscanf(fp, "%255s %d %d %lf", k, &bl, &wg, &ms) == 4) {
+        if (key == k && bl >= 10 && bl <= 14 && wg >= 1 && wg <= 16) {
+          *best_mode = policy_mode | ((uint32_t)bl << 8);
+          *best_wg = wg;
+          hit = true;
+        }
+      }
+      std::fclose(fp);
+      if (hit) return SZNB_OK;
+    }
+  }
+  // buffers for the largest candidate
+  std::vector<uint64_t> caps(nf, 0);
+  uint64_t wsb = 0;
+  for (int bl = 10; bl <= 14; bl++) {
+    std::vector<uint32_t> m(nf, policy_mode | ((uint32_t)bl << 8));
+    wsb = std::max<uint64_t>(wsb, compress_layout(nf, n, m.data()).total);
+    for (int f = 0; f < nf; f++) caps[f] = std::max<uint64_t>(caps[f], compress_bound_impl(n[f], m[f]));
+  }
+  std::vector<void *> outs(nf, nullptr);
+  void *ws = nullptr;
+  uint64_t *lens = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool ok = hipMalloc(&ws, wsb) == hipSuccess && hipMalloc(reinterpret_cast<void **>(&lens), 8ull * nf) == hipSuccess &&
+            hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+  for (int f = 0; ok && f < nf; f++) ok = hipMalloc(&outs[f], caps[f]) == hipSuccess;
+  struct Cand { int bl, wg; float ms; uint64_t bytes; };
+  std::vector<Cand> cands;
+  const int saved_wg = g_wg_per_cu;
+  rc = ok ? SZNB_OK : SZNB_EDEVICE;
+  for (int bl = 10; rc == SZNB_OK && bl <= 14; bl++) {
+    std::vector<uint32_t> m(nf, policy_mode | ((uint32_t)bl << 8));
+    Launch P;
+    DevInfo *d2 = nullptr;
+    rc = compress_prepare(nf, fields, n, eb, m.data(), outs.data(), caps.data(), lens, true, ws, wsb, stream, P, d2);
+    for (int wg : {2, 4, 8, 16}) {
+      if (rc) break;
+      g_wg_per_cu = wg;
+      float best = 1e30f;
+      for (int rep = 0; rep < 4 && rc == SZNB_OK; rep++) {
+        (void)hipEventRecord(e0, stream);
+        rc = compress_run(P, stream, d2);
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) rc = SZNB_EDEVICE;
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep) best = std::min(best, ms);
+      }
+      std::vector<uint64_t> hl(nf);
+      if (rc == SZNB_OK && hipMemcpy(hl.data(), lens, 8ull * nf, hipMemcpyDeviceToHost) != hipSuccess) rc = SZNB_EDEVICE;
+      uint64_t bytes = 0;
+      for (uint64_t v : hl) bytes += v;
+      if (rc == SZNB_OK) cands.push_back({bl, wg, best, bytes});
+    }
+  }
+  g_wg_per_cu = saved_wg;
+  for (void *p : outs) if (p) (void)hipFree(p);
+  if (ws) (void)hipFree(ws);
+  if (lens) (void)hipFree(lens);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  uint64_t smallest = ~0ull;
+  for (const Cand &c : cands) smallest = std::min(smallest, c.bytes);
+  const Cand *pick = nullptr;
+  for (const Cand &c : cands)
+    if ((double)c.bytes <= 1.01 * (double)smallest && (!pick || c.ms < pick->ms)) pick = &c;
+  if (!pick) return SZNB_EDEVICE;
+  *best_mode = policy_mode | ((uint32_t)pick->bl << 8);
+  *best_wg = pick->wg;
+  if (cache_path) {
+    if (FILE *fp = std::fopen(cache_path, "a")) {
+      std::fprintf(fp, "%s %d %d %.4f\n", key.c_str(), pick->bl, pick->wg, pick->ms);
+      std::fclose(fp);
+    }
+  }
+  return SZNB_OK;
 }
 
 template <int E>
@@ -903,6 +1100,28 @@ int sznb_read_status(const void *d_ws, int nf, int *h_status, hipStream_t stream
     if (v != SZNB_OK && first == SZNB_OK) first = v;
   }
   return first;
+}
+
+int sznb_compress_plan(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                       const uint32_t *h_mode, void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
+                       void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *plan_out) {
+  return plan_create(nf, h_fields, h_n, h_eb, h_mode, h_outs, h_caps, d_lens, d_ws, ws_bytes, stream, plan_out);
+}
+int sznb_plan_capture(sznb_plan plan, hipStream_t stream) { return plan_graph(plan, stream); }
+int sznb_plan_launch(sznb_plan plan, hipStream_t stream) { return plan_run(plan, stream); }
+void sznb_plan_destroy(sznb_plan plan) { plan_destroy(plan); }
+
+int sznb_set_workgroups_per_cu(int wg) {
+  if (wg < 1 || wg > 16) return SZNB_EINVAL;
+  g_wg_per_cu = wg;
+  return SZNB_OK;
+}
+int sznb_get_workgroups_per_cu(void) { return g_wg_per_cu; }
+
+int sznb_autotune(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
+                  uint32_t policy_mode, const char *cache_path, uint32_t *h_best_mode, int *h_best_wg,
+                  hipStream_t stream) {
+  return autotune_impl(nf, h_fields, h_n, h_eb, policy_mode, cache_path, h_best_mode, h_best_wg, stream);
 }
 
 int sznb_set_selector(const float *h_params, float tau) { return set_selector_impl(h_params, tau); }

@@ -60,6 +60,13 @@ def lib():
         L.sznb_profile.argtypes = [ctypes.c_int]
         L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
         L.sznb_strerror.argtypes = [ctypes.c_int]
+        L.sznb_compress_plan.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp]
+        L.sznb_plan_capture.argtypes = [_vp, _vp]
+        L.sznb_plan_launch.argtypes = [_vp, _vp]
+        L.sznb_plan_destroy.argtypes = [_vp]
+        L.sznb_plan_destroy.restype = None
+        L.sznb_set_workgroups_per_cu.argtypes = [ctypes.c_int]
+        L.sznb_autotune.argtypes = [ctypes.c_int, _vp, _vp, _vp, ctypes.c_uint32, ctypes.c_char_p, _vp, _vp, _vp]
         L.sznb_set_selector.argtypes = [_vp, ctypes.c_float]
         L.sznb_features_workspace_bytes.argtypes = [ctypes.c_int, _vp, _vp]
         L.sznb_features_workspace_bytes.restype = _u64
@@ -375,3 +382,69 @@ def mlp_infer(params: torch.Tensor, feat: torch.Tensor, stream=None):
                               margin.data_ptr(), _stream(stream))
     _check(rc, "mlp_infer")
     return logits[:nb], choice[:nb], margin[:nb]
+
+
+# ----------------------------------------------------------------- plans
+
+class CompressPlan:
+    """A field table prepared once; launch() enqueues only kernels, capture()
+    records them into a HIP graph that later launches replay.  The input
+    tensors may change in place between launches."""
+
+    def __init__(self, fields: Sequence[torch.Tensor], eb, mode, *, stream=None):
+        self.fields = [_field(x) for x in fields]
+        nf = len(self.fields)
+        self.ebs = list(eb) if isinstance(eb, (list, tuple)) else [float(eb)] * nf
+        self.modes = list(mode) if isinstance(mode, (list, tuple)) else [int(mode)] * nf
+        self.ns = [x.numel() for x in self.fields]
+        dev = self.fields[0].device
+        self.caps = [compress_bound(n, m) for n, m in zip(self.ns, self.modes)]
+        self.outs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in self.caps]
+        self.lens = torch.zeros(nf, dtype=torch.int64, device=dev)
+        self.ws = workspace(compress_workspace_bytes(self.ns, self.modes), dev)
+        self._p = ctypes.c_void_p()
+        rc = lib().sznb_compress_plan(nf, _arr(_vp, [x.data_ptr() for x in self.fields]), _arr(_u64, self.ns),
+                                      _arr(ctypes.c_double, self.ebs), _arr(ctypes.c_uint32, self.modes),
+                                      _arr(_vp, [o.data_ptr() for o in self.outs]), _arr(_u64, self.caps),
+                                      self.lens.data_ptr(), self.ws.data_ptr(), self.ws.numel(), _stream(stream),
+                                      ctypes.byref(self._p))
+        _check(rc, "compress_plan")
+
+    def capture(self, stream):
+        _check(lib().sznb_plan_capture(self._p, _stream(stream)), "plan_capture")
+
+    def launch(self, stream=None):
+        _check(lib().sznb_plan_launch(self._p, _stream(stream)), "plan_launch")
+
+    def streams(self):
+        return [b[:int(v)] for b, v in zip(self.outs, self.lens.cpu())]
+
+    def close(self):
+        if self._p:
+            lib().sznb_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_workgroups_per_cu(wg: int) -> None:
+    _check(lib().sznb_set_workgroups_per_cu(int(wg)), "set_workgroups_per_cu")
+
+
+def autotune(fields: Sequence[torch.Tensor], eb, policy_mode: int, cache_path=None, stream=None):
+    """(mode with the chosen block size, workgroups per CU) for these fields."""
+    fields = [_field(x) for x in fields]
+    nf = len(fields)
+    ebs = list(eb) if isinstance(eb, (list, tuple)) else [float(eb)] * nf
+    mode = ctypes.c_uint32(0)
+    wg = ctypes.c_int(0)
+    rc = lib().sznb_autotune(nf, _arr(_vp, [x.data_ptr() for x in fields]), _arr(_u64, [x.numel() for x in fields]),
+                             _arr(ctypes.c_double, ebs), int(policy_mode),
+                             None if cache_path is None else str(cache_path).encode(), ctypes.byref(mode),
+                             ctypes.byref(wg), _stream(stream))
+    _check(rc, "autotune")
+    return int(mode.value), int(wg.value)
