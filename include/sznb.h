@@ -125,6 +125,14 @@ typedef struct sznb_plan_s *sznb_plan;
 int sznb_compress_plan(int nf, const float *const *h_fields, const uint64_t *h_n, const double *h_eb,
                        const uint32_t *h_mode, void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
                        void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *plan_out);
+/* Decompression plan of a table of streams (as sznb_decompress_batch): the
+ * headers are read once here (block size, codebook sizes) to lay out the
+ * decoder; launches then enqueue kernels only.  Streams given to a later
+ * launch may be new contents of the same buffers; one whose block size
+ * exceeds the largest planned one is reported as SZNB_ECORRUPT. */
+int sznb_decompress_plan(int nf, const void *const *h_streams, const uint64_t *h_lens, float *const *h_outs,
+                         const uint64_t *h_n, void *d_ws, uint64_t ws_bytes, hipStream_t stream,
+                         sznb_plan *plan_out);
 int sznb_plan_capture(sznb_plan plan, hipStream_t stream);
 int sznb_plan_launch(sznb_plan plan, hipStream_t stream);
 void sznb_plan_destroy(sznb_plan plan);

@@ -27,7 +27,8 @@ template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, u
 __global__ void k_final(const CField *, int);
 uint64_t hscratch_bytes_host();
 
-__global__ void d_prep(const DField *);
+__global__ void d_prep(const DField *, uint32_t);
+__global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
 __global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int);
@@ -438,8 +439,9 @@ static int compress_impl(int nf, const float *const *fields, const uint64_t *n, 
 }  // namespace sznb
 
 struct sznb_plan_s {
-  sznb::Launch P;
+  sznb::Launch P;                 // compression plan
   sznb::DevInfo *dv = nullptr;
+  void *dplan = nullptr;          // decompression plan (a DLaunch) instead, when set
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -461,11 +463,17 @@ static int plan_create(int nf, const float *const *fields, const uint64_t *n, co
   return SZNB_OK;
 }
 
+static int dplan_run(void *dplan, hipStream_t stream);
+
+static int plan_body(sznb_plan p, hipStream_t stream) {
+  return p->dplan ? dplan_run(p->dplan, stream) : compress_run(p->P, stream, p->dv);
+}
+
 static int plan_graph(sznb_plan p, hipStream_t stream) {
   if (!p) return SZNB_EINVAL;
   if (p->exec) return SZNB_OK;
   if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SZNB_EDEVICE;
-  const int rc = compress_run(p->P, stream, p->dv);
+  const int rc = plan_body(p, stream);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(stream, &g);
   if (rc || ec != hipSuccess || !g) {
@@ -484,13 +492,16 @@ static int plan_graph(sznb_plan p, hipStream_t stream) {
 static int plan_run(sznb_plan p, hipStream_t stream) {
   if (!p) return SZNB_EINVAL;
   if (p->exec) return hipGraphLaunch(p->exec, stream) == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
-  return compress_run(p->P, stream, p->dv);
+  return plan_body(p, stream);
 }
+
+static void dplan_free(void *dplan);
 
 static void plan_destroy(sznb_plan p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->dplan) dplan_free(p->dplan);
   delete p;
 }
 
@@ -700,7 +711,7 @@ static int set_selector_impl(const float *h_params, float tau) {
 // ---------------------------------------------------------- decompress
 
 struct DLayout {
-  uint64_t gctl, states, fields, tbase, total;
+  uint64_t gctl, states, fields, tbase, heads, total;
   std::vector<uint64_t> boff, order, lut, slow, syms, nbmax;
 };
 
@@ -711,6 +722,7 @@ static DLayout decompress_layout(int nf, const uint64_t *n) {
   L.states = o; o = al256(o + kStateStride * nf);
   L.fields = o; o = al256(o + sizeof(DField) * nf);
   L.tbase = o; o = al256(o + 4ull * (3 * nf + 1));
+  L.heads = o; o = al256(o + 16ull * nf);
   L.boff.resize(nf); L.order.resize(nf); L.lut.resize(nf); L.slow.resize(nf); L.syms.resize(nf); L.nbmax.resize(nf);
   for (int f = 0; f < nf; f++) {
     L.nbmax[f] = (n[f] + 1023) / 1024;
@@ -724,38 +736,35 @@ static DLayout decompress_layout(int nf, const uint64_t *n) {
   return L;
 }
 
-static int decompress_impl(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
-                           const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+// Everything a decompression launch needs beyond the workspace.
+struct DLaunch {
+  int nf = 0;
+  uint8_t *ws = nullptr;
+  DLayout L;
+  uint32_t smax = 1024, symcap = 0, dw = 1;
+  size_t lds = 0;
+  int grid = 1;
+};
+
+// Writes the stream descriptors, reads block size and codebook sizes of
+// every header (one gather kernel, one copy back) and chooses the decoder's
+// LDS layout: most resident waves per CU under the LDS of a CU, with the
+// tables once per workgroup and one code region per wave (1 KiB stays free
+// for the kernel's static LDS and alignment).
+static int decompress_prepare(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
+                              const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, DLaunch &P) {
   if (nf <= 0 || !d_ws) return SZNB_EINVAL;
   DevInfo *dv;
   int rc = dev_init(&dv);
   if (rc) return rc;
   DLayout L = decompress_layout(nf, n);
   if (ws_bytes < L.total) return SZNB_ENOSPC;
-  // block sizes from the headers (host copy of 128 bytes per stream)
-  std::vector<uint8_t> hdr(128ull * nf);
+  uint8_t *ws = static_cast<uint8_t *>(d_ws);
+  std::vector<DField> hf(nf);
   for (int f = 0; f < nf; f++) {
     if (!streams[f] || lens[f] < kHdr || (reinterpret_cast<uintptr_t>(streams[f]) & 7u)) return SZNB_EINVAL;
     if (n[f] && (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 15u))) return SZNB_EINVAL;
     if (n[f] >= SZNB_MAX_N) return SZNB_EINVAL;
-    if (hipMemcpyAsync(hdr.data() + 128ull * f, streams[f], 128, hipMemcpyDeviceToHost, stream) != hipSuccess)
-      return SZNB_EDEVICE;
-  }
-  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
-  uint32_t smax = 1024, nsym_max = 0;
-  for (int f = 0; f < nf; f++) {
-    uint32_t S;
-    std::memcpy(&S, hdr.data() + 128ull * f + H_S, 4);
-    if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
-    for (int k = 0; k < 3; k++) {
-      uint32_t ns;
-      std::memcpy(&ns, hdr.data() + 128ull * f + H_NSYM + 4 * k, 4);
-      if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
-    }
-  }
-  uint8_t *ws = static_cast<uint8_t *>(d_ws);
-  std::vector<DField> hf(nf);
-  for (int f = 0; f < nf; f++) {
     DField &d = hf[f];
     std::memset(&d, 0, sizeof d);
     d.in = static_cast<const uint8_t *>(streams[f]);
@@ -772,14 +781,22 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
   }
   if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(DField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
     return SZNB_EDEVICE;
-  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
   const DField *D = reinterpret_cast<const DField *>(ws + L.fields);
-  uint32_t *tbase = reinterpret_cast<uint32_t *>(ws + L.tbase);
-  SZNB_LAUNCH("d_prep", d_prep, dim3(nf), dim3(kThreads), 0, stream, D);
-  SZNB_LAUNCH("d_tables", d_tables, dim3(3 * nf), dim3(kThreads), 0, stream, D);
-  // waves per workgroup and symbol table placement: most resident waves per
-  // CU under the LDS of a CU (tables once per workgroup, one region per wave)
-  // (1 KiB stays free for the kernel's static LDS and alignment)
+  SZNB_LAUNCH("d_heads", d_heads, dim3((nf + 255) / 256), dim3(256), 0, stream, D, nf,
+              reinterpret_cast<uint32_t *>(ws + L.heads));
+  std::vector<uint32_t> heads(4ull * nf);
+  if (hipMemcpyAsync(heads.data(), ws + L.heads, 16ull * nf, hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return SZNB_EDEVICE;
+  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  uint32_t smax = 1024, nsym_max = 0;
+  for (int f = 0; f < nf; f++) {
+    const uint32_t S = heads[4 * f];
+    if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
+    for (int k = 0; k < 3; k++) {
+      const uint32_t ns = heads[4 * f + 1 + k];
+      if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
+    }
+  }
   const size_t lds_cu = (dv->lds_per_block ? dv->lds_per_block : 65536) - 1024;
   const size_t tables = 4ull * (1u << kLutBits) + 4ull * 64 + 8ull * 32;
   uint32_t symcap = nsym_max;
@@ -799,13 +816,58 @@ static int decompress_impl(int nf, const void *const *streams, const uint64_t *l
                             (int)lds) != hipSuccess)
       return SZNB_EDEVICE;
   }
-  uint32_t *ticket = &reinterpret_cast<GCtl *>(ws + L.gctl)->ticket;
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, nf, dw, tbase, ticket);
-  SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, nf);
-  const int grid = dv->cus * (int)std::max<size_t>(1, lds_cu / lds);
-  SZNB_LAUNCH("d_decode", d_decode, dim3(grid), dim3(kWave * dw), lds, stream, D, nf, tbase, dw, smax, symcap,
-              ticket);
+  P.nf = nf;
+  P.ws = ws;
+  P.L = L;
+  P.smax = smax;
+  P.symcap = symcap;
+  P.dw = dw;
+  P.lds = lds;
+  P.grid = dv->cus * (int)std::max<size_t>(1, lds_cu / lds);
+  return SZNB_OK;
+}
+
+// Kernels only (capturable): streams whose block size exceeds the planned
+// one are reported corrupt rather than decoded.
+static int decompress_run(const DLaunch &P, hipStream_t stream) {
+  const DField *D = reinterpret_cast<const DField *>(P.ws + P.L.fields);
+  uint32_t *tbase = reinterpret_cast<uint32_t *>(P.ws + P.L.tbase);
+  uint32_t *ticket = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->ticket;
+  SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(kThreads), 0, stream, D, P.smax);
+  SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket);
+  SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf);
+  SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.dw, P.smax,
+              P.symcap, ticket);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
+
+static int decompress_impl(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
+                           const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
+  DLaunch P;
+  int rc = decompress_prepare(nf, streams, lens, outs, n, d_ws, ws_bytes, stream, P);
+  if (rc) return rc;
+  return decompress_run(P, stream);
+}
+
+static int dplan_run(void *dplan, hipStream_t stream) {
+  return decompress_run(*static_cast<DLaunch *>(dplan), stream);
+}
+static void dplan_free(void *dplan) { delete static_cast<DLaunch *>(dplan); }
+
+static int dplan_create(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
+                        const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *out) {
+  if (!out) return SZNB_EINVAL;
+  *out = nullptr;
+  DLaunch *dl = new (std::nothrow) DLaunch;
+  sznb_plan p = new (std::nothrow) sznb_plan_s;
+  if (!dl || !p) { delete dl; delete p; return SZNB_EDEVICE; }
+  int rc = decompress_prepare(nf, streams, lens, outs, n, d_ws, ws_bytes, stream, *dl);
+  if (rc == SZNB_OK && hipGetDevice(&p->device) != hipSuccess) rc = SZNB_EDEVICE;
+  if (rc) { delete dl; delete p; return rc; }
+  p->dplan = dl;
+  *out = p;
+  return SZNB_OK;
 }
 
 // ------------------------------------------------------------ MD modes
@@ -1106,6 +1168,10 @@ int sznb_compress_plan(int nf, const float *const *h_fields, const uint64_t *h_n
                        const uint32_t *h_mode, void *const *h_outs, const uint64_t *h_caps, uint64_t *d_lens,
                        void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *plan_out) {
   return plan_create(nf, h_fields, h_n, h_eb, h_mode, h_outs, h_caps, d_lens, d_ws, ws_bytes, stream, plan_out);
+}
+int sznb_decompress_plan(int nf, const void *const *h_streams, const uint64_t *h_lens, float *const *h_outs,
+                         const uint64_t *h_n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, sznb_plan *plan_out) {
+  return dplan_create(nf, h_streams, h_lens, h_outs, h_n, d_ws, ws_bytes, stream, plan_out);
 }
 int sznb_plan_capture(sznb_plan plan, hipStream_t stream) { return plan_graph(plan, stream); }
 int sznb_plan_launch(sznb_plan plan, hipStream_t stream) { return plan_run(plan, stream); }

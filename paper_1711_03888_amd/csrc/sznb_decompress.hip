@@ -26,7 +26,20 @@ __device__ inline uint16_t rd16(const uint8_t *p, uint64_t off) {
 
 // ---------------------------------------------------------------- prep
 
-__global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D) {
+// block size and codebook sizes of every header (for the launch layout)
+__global__ void d_heads(const DField *__restrict__ D, int nf, uint32_t *heads) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const DField &df = D[f];
+  uint32_t v[4] = {0u, 0u, 0u, 0u};
+  if (df.in_len >= (uint64_t)kHdr && rd32(df.in, H_MAGIC) == kMagic) {
+    v[0] = rd32(df.in, H_S);
+    for (int k = 0; k < 3; k++) v[1 + k] = rd32(df.in, H_NSYM + 4 * k);
+  }
+  for (int k = 0; k < 4; k++) heads[4 * f + k] = v[k];
+}
+
+__global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D, uint32_t smax) {
   const DField &df = D[blockIdx.x];
   DState *st = df.st;
   const uint8_t *in = df.in;
@@ -47,7 +60,7 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D)
       S = rd32(in, H_S);
       nb = rd32(in, H_NB);
       total = rd64(in, H_TOTAL);
-      if (policy > 3 || n != df.n || total > df.in_len || S < 1024 || S > 16384 || (S & (S - 1))) bad = 1;
+      if (policy > 3 || n != df.n || total > df.in_len || S < 1024 || S > smax || (S & (S - 1))) bad = 1;
     }
     st->policy = policy; st->S = S; st->n = n;
     st->mn = __uint_as_float(bad ? 0u : rd32(in, H_MN));

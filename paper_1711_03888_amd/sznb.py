@@ -61,6 +61,7 @@ def lib():
         L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
         L.sznb_strerror.argtypes = [ctypes.c_int]
         L.sznb_compress_plan.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp]
+        L.sznb_decompress_plan.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp]
         L.sznb_plan_capture.argtypes = [_vp, _vp]
         L.sznb_plan_launch.argtypes = [_vp, _vp]
         L.sznb_plan_destroy.argtypes = [_vp]
@@ -418,6 +419,41 @@ class CompressPlan:
 
     def streams(self):
         return [b[:int(v)] for b, v in zip(self.outs, self.lens.cpu())]
+
+    def close(self):
+        if self._p:
+            lib().sznb_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DecompressPlan:
+    """Streams (device uint8 tensors) laid out once for decoding; launch()
+    enqueues only kernels and capture() records them into a HIP graph."""
+
+    def __init__(self, streams: Sequence[torch.Tensor], ns: Sequence[int], *, outs=None, stream=None):
+        self.streams = list(streams)
+        self.ns = list(ns)
+        dev = self.streams[0].device
+        self.outs = outs if outs is not None else [torch.empty(n, dtype=torch.float32, device=dev) for n in self.ns]
+        self.ws = workspace(decompress_workspace_bytes(self.ns), dev)
+        self._p = ctypes.c_void_p()
+        rc = lib().sznb_decompress_plan(len(self.streams), _arr(_vp, [s.data_ptr() for s in self.streams]),
+                                        _arr(_u64, [s.numel() for s in self.streams]),
+                                        _arr(_vp, [o.data_ptr() for o in self.outs]), _arr(_u64, self.ns),
+                                        self.ws.data_ptr(), self.ws.numel(), _stream(stream), ctypes.byref(self._p))
+        _check(rc, "decompress_plan")
+
+    def capture(self, stream):
+        _check(lib().sznb_plan_capture(self._p, _stream(stream)), "plan_capture")
+
+    def launch(self, stream=None):
+        _check(lib().sznb_plan_launch(self._p, _stream(stream)), "plan_launch")
 
     def close(self):
         if self._p:

@@ -94,3 +94,47 @@ def test_autotune_and_cache(tmp_path):
     finally:
         sznb.set_workgroups_per_cu(8)
     assert got == _ref(xs, mode)
+
+
+def test_decompress_plan_graph_replays():
+    mode = sznb.PRED_BESTFIT | sznb.EB_REL
+    xs = _fields()
+    dev = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs]
+    cplan = sznb.CompressPlan(dev, EBS, mode)
+    cplan.launch()
+    torch.cuda.synchronize()
+    streams = cplan.streams()
+    # decode buffers sized for the largest stream a replay may hold
+    bufs = [torch.zeros(c, dtype=torch.uint8, device="cuda") for c in cplan.caps]
+    for b, s in zip(bufs, streams):
+        b[:s.numel()].copy_(s)
+    dplan = sznb.DecompressPlan(bufs, [x.size for x in xs])
+    dplan.launch()
+    torch.cuda.synchronize()
+    for y, s in zip(dplan.outs, streams):
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.decompress(bytes(s.cpu().numpy())).view(np.uint32))
+    side = torch.cuda.Stream()
+    dplan.capture(side)
+    for rep in range(3):
+        print("decode replay %d" % rep, flush=True)
+        with torch.no_grad():
+            for t in dev:
+                t.mul_(0.999).add_(0.25)
+        torch.cuda.synchronize()
+        cplan.launch()
+        torch.cuda.synchronize()
+        new = cplan.streams()
+        for b, s in zip(bufs, new):
+            b.zero_()
+            b[:s.numel()].copy_(s)
+        torch.cuda.synchronize()
+        side.wait_stream(torch.cuda.current_stream())
+        dplan.launch(side)
+        side.synchronize()
+        first, st = sznb.read_status(dplan.ws, len(dev))
+        assert first == sznb.OK, st
+        for y, s in zip(dplan.outs, new):
+            ref = oracle.decompress(bytes(s.cpu().numpy()))
+            assert np.array_equal(y.cpu().numpy().view(np.uint32), ref.view(np.uint32))
+    dplan.close()
+    cplan.close()
