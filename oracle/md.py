@@ -21,6 +21,9 @@ Readings where the paper is silent:
 * B = max over the three coordinates of bitlen(P_c) bits per coordinate, at
   most 21 (a 63-bit key); digit j of the key holds (x_j, y_j, z_j), x highest;
 * segments are index ranges of 16384 particles (Tables 4 and 5);
+* the coordinate stream also stores, for every 256 keys of a segment, the
+  bit offset where their code starts, so that a decoder can start at each
+  of them (the entry for key 0 of the segment is 0);
 * CPC2000's "adaptive variable-length encoding with status bits" (Sec. 2,
   Sec. 5.2) is read as Rice coding of the key deltas of each sorted segment:
   parameter r = argmin_r sum(floor(d / 2^r) + 1 + r) (ties to the smaller r),
@@ -39,6 +42,7 @@ import numpy as np
 from . import EB_REL, LV, compress, decompress, lattice, params, reconstruct_array
 
 SEG = 16384
+SUB = 256  # keys per decoder entry point
 SPEED, TRADEOFF, COMPRESSION = 0, 1, 2
 PRX_IGNORED = 6  # Table 5: segment 16384, six ignored 3-bit digits
 CPC_ESC_Q = 32
@@ -110,8 +114,9 @@ def pack_fields(values, nbits):
     return words, total
 
 
-def cpc_encode_segment(keys_sorted, keybits):
-    """First key raw, 6-bit Rice parameter, then the Rice-coded deltas."""
+def cpc_encode_segment(keys_sorted, keybits, with_entries=False):
+    """First key raw, 6-bit Rice parameter, then the Rice-coded deltas;
+    optionally also the bit offset of key 0, SUB, 2 SUB, ... of the segment."""
     d = np.diff(keys_sorted.astype(np.uint64))
     r = rice_parameter(d, keybits) if d.size else 0
     q = (d >> np.uint64(r)).astype(np.int64)
@@ -129,7 +134,14 @@ def cpc_encode_segment(keys_sorted, keybits):
     vals[1], lens[1] = np.uint64(r), 6
     vals[2::2], lens[2::2] = unary_v, unary_n
     vals[3::2], lens[3::2] = tail_v, tail_n
-    return pack_fields(vals, lens)
+    words, total = pack_fields(vals, lens)
+    if not with_entries:
+        return words, total
+    # bit offset where key i starts: key 0 at 0, key i >= 1 after the first
+    # key, the parameter and deltas 1 .. i - 1
+    per_key = np.concatenate([[keybits + 6], unary_n + tail_n]).astype(np.int64)
+    starts = np.concatenate([[0], np.cumsum(per_key)[:-1]])
+    return words, total, starts[::SUB].astype(np.uint32)
 
 
 def cpc_decode_segment(words, count, keybits):
@@ -175,20 +187,23 @@ def _coord_stream(coords, eb_rel, perm_keys, B):
     keybits = 3 * B
     nseg = (n + SEG - 1) // SEG
     pr = [params(c, eb_rel) for c in coords]
-    seg_words, seg_bits = [], []
+    seg_words, seg_bits, entries = [], [], []
     for s in range(nseg):
-        w, nb = cpc_encode_segment(perm_keys[s * SEG:(s + 1) * SEG], keybits)
+        w, nb, ent = cpc_encode_segment(perm_keys[s * SEG:(s + 1) * SEG], keybits, with_entries=True)
         seg_words.append(w)
         seg_bits.append(nb)
-    head = struct.pack(CP_FMT, b"SZCP", 1, B, 0, n, nseg, SEG, keybits,
+        entries.append(ent)
+    head = struct.pack(CP_FMT, b"SZCP", 2, B, 0, n, nseg, SEG, keybits,
                        pr[0]["mn"], pr[0]["mx"], pr[1]["mn"], pr[1]["mx"], pr[2]["mn"], pr[2]["mx"],
                        pr[0]["eb_abs"], pr[1]["eb_abs"], pr[2]["eb_abs"],
                        pr[0]["step"], pr[1]["step"], pr[2]["step"])
     head += b"\0" * (-len(head) % 8)
     tab = np.array(seg_bits, np.uint32).tobytes()
     tab += b"\0" * (-len(tab) % 8)
+    ent = np.concatenate(entries).astype("<u4").tobytes()
+    ent += b"\0" * (-len(ent) % 8)
     body = b"".join(w.astype("<u4").tobytes() for w in seg_words)
-    return head + tab + body
+    return head + tab + ent + body
 
 
 def compress_md(fields, eb_rel, md_mode):
@@ -248,19 +263,30 @@ def decode_coord_stream(sb):
     magic, ver, B, _, n, nseg, seg, keybits = vals[:8]
     mnmx = vals[8:14]
     steps = vals[17:20]
-    assert magic == b"SZCP" and ver == 1
+    assert magic == b"SZCP" and ver == 2
     hlen = struct.calcsize(CP_FMT)
     hlen += -hlen % 8
     seg_bits = np.frombuffer(sb, np.uint32, count=nseg, offset=hlen)
     o = hlen + 4 * nseg
     o += -o % 8
+    counts = [min(seg, n - s * seg) for s in range(nseg)]
+    nent = sum(-(-c // SUB) for c in counts)
+    entries = np.frombuffer(sb, "<u4", count=nent, offset=o)
+    o += 4 * nent
+    o += -o % 8
     keys = []
+    e0 = 0
     for s in range(nseg):
         nw = (int(seg_bits[s]) + 31) // 32
         words = np.frombuffer(sb, "<u4", count=nw, offset=o)
         o += 4 * nw
-        cnt = min(seg, n - s * seg)
-        keys.append(cpc_decode_segment(words, cnt, keybits))
+        cnt = counts[s]
+        seg_keys = cpc_decode_segment(words, cnt, keybits)
+        # the entry points are where the code of every SUB-th key starts
+        _, _, ent = cpc_encode_segment(seg_keys, keybits, with_entries=True)
+        assert np.array_equal(ent, entries[e0:e0 + ent.size])
+        e0 += ent.size
+        keys.append(seg_keys)
     key = np.concatenate(keys)
     ps = deinterleave(key, B)
     # reconstruction x~ = fl32(fma(p, step, mn)) per coordinate

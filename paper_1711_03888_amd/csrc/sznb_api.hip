@@ -30,8 +30,8 @@ uint64_t hscratch_bytes_host();
 __global__ void d_prep(const DField *, uint32_t);
 __global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
-__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
-__global__ void d_const(const DField *, int);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *, uint32_t *);
+__global__ void d_const(const DField *, int, const uint32_t *);
 __global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *);
 
 template <int E>
@@ -835,8 +835,9 @@ static int decompress_run(const DLaunch &P, hipStream_t stream) {
   uint32_t *ticket = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->ticket;
   SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(kThreads), 0, stream, D, P.smax);
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket);
-  SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf);
+  uint32_t *nconst = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->pad[0];
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket, nconst);
+  SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf, nconst);
   SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.dw, P.smax,
               P.symcap, ticket);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
@@ -907,7 +908,7 @@ static MdLayout md_layout(int nf, uint64_t n) {
   L.segr = o; o = al256(o + 4 * L.nseg);
   L.segb = o; o = al256(o + 4 * L.nseg);
   L.segw = o; o = al256(o + 4 * L.nseg);
-  L.coord_cap = 104 + align8(4 * L.nseg) + 12 * n + 64 + 8 * L.nseg;
+  L.coord_cap = 104 + align8(4 * L.nseg) + align8(4 * (n / 256 + L.nseg)) + 12 * n + 64 + 8 * L.nseg;
   L.coord = o; o = al256(o + L.coord_cap);
   std::vector<uint64_t> nn(nf, n);
   std::vector<uint32_t> mm(nf, kMdMode);
@@ -1057,7 +1058,7 @@ static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_
   if (hipMemsetAsync(dstatus, 0, 4, s) != hipSuccess) return SZNB_EDEVICE;
   int first = 0;
   if (md_mode == 2) {
-    SZNB_LAUNCH("cpc_decode", cpc_decode, dim3((unsigned)((L.nseg + 63) / 64)), dim3(64), 0, s, in + offs[0],
+    SZNB_LAUNCH("cpc_decode", cpc_decode, dim3((unsigned)L.nseg), dim3(kWave), 0, s, in + offs[0],
                 ends[0] - offs[0], n, outs[0], outs[1], outs[2], dstatus);
     first = 1;
   }

@@ -220,19 +220,24 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
 // tbase[p] for p = 3 f + k: first decode task of (stream f, predictor k); a
 // task is up to `dw` consecutive blocks of one group.
 __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t dw,
-                                                    uint32_t *tbase, uint32_t *ticket) {
+                                                    uint32_t *tbase, uint32_t *ticket, uint32_t *nconst) {
   __shared__ uint32_t s_tot[kThreads / kWave];
+  __shared__ uint32_t s_const;
   const int t = threadIdx.x, w = t / kWave;
   const int np = 3 * nf;
   const int per = (np + kThreads - 1) / kThreads;
-  uint32_t loc = 0;
+  if (t == 0) s_const = 0;
+  __syncthreads();
+  uint32_t loc = 0, ncon = 0;
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
       const DState *st = D[p / 3].st;
       if (st->status == 0 && !st->is_const) loc += (st->grp_count[p % 3] + dw - 1) / dw;
+      if (p % 3 == 0 && st->status == 0 && st->is_const) ncon++;
     }
   }
+  if (ncon) atomicAdd(&s_const, ncon);
   const uint32_t inc = wave_incl_scan(loc);
   if (lane_id() == kWave - 1) s_tot[w] = inc;
   __syncthreads();
@@ -247,9 +252,12 @@ __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D
     }
   }
   if (t == kThreads - 1) { tbase[np] = run; *ticket = 0; }
+  __syncthreads();
+  if (t == 0) *nconst = s_const;
 }
 
-__global__ void d_const(const DField *__restrict__ D, int nf) {
+__global__ void d_const(const DField *__restrict__ D, int nf, const uint32_t *nconst) {
+  if (*nconst == 0) return;  // no constant stream in the table
   for (int f = 0; f < nf; f++) {
     const DField &df = D[f];
     const DState *st = df.st;

@@ -16,13 +16,15 @@
 //   cpc_count   per segment: key deltas, Rice parameter, coded size
 //   cpc_offsets segment word offsets, coordinate stream header
 //   cpc_pack    per segment: first key, parameter, Rice-coded deltas
-//   cpc_decode  one lane per segment: keys back, then lattice values
+//   cpc_decode  one wave per segment, one lane per 256 keys (entry points
+//               stored in the stream): keys back, then lattice values
 //   md_assemble container header and sub-stream copies
 #include "sznb_internal.h"
 
 namespace sznb {
 
 constexpr uint32_t kSeg = 16384;
+constexpr uint32_t kSub = 256;   // keys per decoder entry point (kSeg / kSub = 64 lanes)
 constexpr uint32_t kEscQ = 32;   // quotients from 32 on are escaped
 constexpr int kMT = 1024;
 constexpr int kMW = kMT / kWave;
@@ -209,10 +211,16 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *key, uint64_t n
 }
 
 // Coordinate stream header (104 bytes):
-//   "SZCP" u16 1 u8 B u8 0 u64 n u32 nseg u32 seg u32 keybits
+//   "SZCP" u16 2 u8 B u8 0 u64 n u32 nseg u32 seg u32 keybits
 //   f32 (mn, mx) x3, f64 eb_abs x3, f64 step x3, padding to 104
-// then u32 seg_bits[nseg] (padded to 8 bytes), then the segments' words.
+// then u32 seg_bits[nseg] (padded to 8 bytes), then the entry points: for
+// every segment and every 256 keys of it, u32 bit offset (from the segment
+// start) of that key's code (padded to 8 bytes), then the segments' words.
 constexpr uint32_t kCpHdr = 104;
+__host__ __device__ inline uint64_t cpc_entries(uint64_t n) {  // entry points of all segments
+  const uint64_t nseg = (n + kSeg - 1) / kSeg;
+  return nseg ? (nseg - 1) * (kSeg / kSub) + (n - (nseg - 1) * kSeg + kSub - 1) / kSub : 0;
+}
 
 __global__ void cpc_offsets(const uint32_t *seg_bits, uint32_t nseg_max, uint64_t n, MdCtl *ctl, const FState *s0,
                             const FState *s1, const FState *s2, uint8_t *cs, uint32_t *seg_woff) {
@@ -224,11 +232,11 @@ __global__ void cpc_offsets(const uint32_t *seg_bits, uint32_t nseg_max, uint64_
     seg_woff[s] = o;
     o += (seg_bits[s] + 31) / 32;
   }
-  const uint64_t tab = align8((uint64_t)4 * nseg);
+  const uint64_t tab = align8((uint64_t)4 * nseg) + align8(4ull * cpc_entries(n));
   ctl->coord_bytes = kCpHdr + tab + 4ull * o;
   for (uint32_t i = 0; i < kCpHdr; i += 4) *reinterpret_cast<uint32_t *>(cs + i) = 0u;
   *reinterpret_cast<uint32_t *>(cs + 0) = 0x50435A53u;  // "SZCP"
-  *reinterpret_cast<uint32_t *>(cs + 4) = 1u | (ctl->B << 16);
+  *reinterpret_cast<uint32_t *>(cs + 4) = 2u | (ctl->B << 16);
   *reinterpret_cast<uint32_t *>(cs + 8) = (uint32_t)n;
   *reinterpret_cast<uint32_t *>(cs + 12) = (uint32_t)(n >> 32);
   *reinterpret_cast<uint32_t *>(cs + 16) = nseg;
@@ -247,6 +255,8 @@ __global__ void cpc_offsets(const uint32_t *seg_bits, uint32_t nseg_max, uint64_
   }
   for (uint32_t s2i = 0; s2i < nseg; s2i++) *reinterpret_cast<uint32_t *>(cs + kCpHdr + 4ull * s2i) = seg_bits[s2i];
   if (nseg & 1u) *reinterpret_cast<uint32_t *>(cs + kCpHdr + 4ull * nseg) = 0u;
+  const uint64_t ne = cpc_entries(n);
+  if (ne & 1u) *reinterpret_cast<uint32_t *>(cs + kCpHdr + align8(4ull * nseg) + 4ull * ne) = 0u;
 }
 
 // bit writer over LDS-free global words: whole words are stored, words that
@@ -288,8 +298,10 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *key, uint64_t n,
   const uint32_t m = (uint32_t)min((uint64_t)kSeg, n - base);
   const uint32_t kb = ctl->keybits, r = seg_r[seg];
   const int t = threadIdx.x, w = t / kWave;
-  const uint64_t tab = align8((uint64_t)4 * ctl->nseg);
-  uint32_t *words = reinterpret_cast<uint32_t *>(cs + kCpHdr + tab) + seg_woff[seg];
+  const uint64_t etab = kCpHdr + align8((uint64_t)4 * ctl->nseg);
+  const uint64_t tab = etab + align8(4ull * cpc_entries(n));
+  uint32_t *words = reinterpret_cast<uint32_t *>(cs + tab) + seg_woff[seg];
+  uint32_t *ent = reinterpret_cast<uint32_t *>(cs + etab) + (uint64_t)seg * (kSeg / kSub);
   const uint32_t nw = (seg_bits[seg] + 31) / 32;
   for (uint32_t i = t; i < nw; i += kMT) words[i] = 0u;
   __syncthreads();
@@ -313,6 +325,7 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *key, uint64_t n,
     b.first_word = pre >> 5;
     b.last_word = (pre + mine - 1) >> 5;
     for (uint32_t i = lo; i < hi; i++) {
+      if ((i & (kSub - 1)) == 0) ent[i / kSub] = (uint32_t)(b.pos + b.na);
       if (i == 0) {
         wb_put_wide(b, key[base], kb);
         wb_put(b, r, 6);
@@ -335,23 +348,27 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *key, uint64_t n,
   }
 }
 
-// one lane per segment: keys back from the Rice code, then the coordinates.
-// Every read is checked against the segment's bit count and the stream
-// length; a stream that fails a check sets ECORRUPT.
-__global__ void cpc_decode(const uint8_t *cs, uint64_t cs_len, uint64_t n, float *ox, float *oy, float *oz,
-                           int *status) {
-  if (cs_len < kCpHdr) { if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
+// One wave per segment, one lane per 256 keys: each lane starts at its entry
+// point, sums its deltas (pass 1), the wave scans the sums, and each lane
+// decodes again writing keys and coordinates (pass 2).  Every read is checked
+// against the segment's bit count and the stream length, and every lane must
+// end exactly at the next lane's entry point; a stream that fails a check
+// sets ECORRUPT.
+__global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t cs_len, uint64_t n, float *ox,
+                                                    float *oy, float *oz, int *status) {
+  const uint32_t seg = blockIdx.x, lane = threadIdx.x;
+  if (cs_len < kCpHdr) { if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
   const uint32_t nseg = *reinterpret_cast<const uint32_t *>(cs + 16);
   const uint32_t kb = *reinterpret_cast<const uint32_t *>(cs + 24);
   const uint64_t nhdr = (uint64_t)*reinterpret_cast<const uint32_t *>(cs + 8) |
                         ((uint64_t)*reinterpret_cast<const uint32_t *>(cs + 12) << 32);
-  const uint64_t tab = align8(4ull * nseg);
-  if (*reinterpret_cast<const uint32_t *>(cs) != 0x50435A53u || nhdr != n || nseg != (n + kSeg - 1) / kSeg ||
-      kb > 63 || kCpHdr + tab > cs_len) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+  const uint64_t etab = kCpHdr + align8(4ull * nseg);
+  const uint64_t tab = etab + align8(4ull * cpc_entries(n));
+  if (*reinterpret_cast<const uint32_t *>(cs) != 0x50435A53u || (*reinterpret_cast<const uint32_t *>(cs + 4) & 0xffffu) != 2u ||
+      nhdr != n || nseg != (n + kSeg - 1) / kSeg || kb > 63 || kb == 0 || tab > cs_len) {
+    if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
     return;
   }
-  const uint32_t seg = blockIdx.x * blockDim.x + threadIdx.x;
   if (seg >= nseg) return;
   float mn[3];
   double step[3];
@@ -365,13 +382,15 @@ __global__ void cpc_decode(const uint8_t *cs, uint64_t cs_len, uint64_t n, float
   uint64_t woff = 0;
   for (uint32_t s = 0; s < seg; s++) woff += (sb[s] + 31) / 32;
   const uint64_t nbits = sb[seg];
-  const uint64_t avail = (cs_len - kCpHdr - tab) / 4;
-  if (woff + (nbits + 31) / 32 > avail) { atomicCAS(status, 0, SZNB_ECORRUPT); return; }
-  const uint32_t *wp = reinterpret_cast<const uint32_t *>(cs + kCpHdr + tab) + woff;
+  const uint64_t avail = (cs_len - tab) / 4;
+  bool bad = woff + (nbits + 31) / 32 > avail;
+  const uint32_t *wp = reinterpret_cast<const uint32_t *>(cs + tab) + woff;
+  const uint32_t *ent = reinterpret_cast<const uint32_t *>(cs + etab) + (uint64_t)seg * (kSeg / kSub);
   const uint64_t base = (uint64_t)seg * kSeg;
   const uint32_t m = (uint32_t)min((uint64_t)kSeg, n - base);
+  const uint32_t k0 = lane * kSub, k1 = min(m, k0 + kSub);  // this lane's keys
+  const bool active = k0 < m;
   uint64_t pos = 0;
-  bool bad = false;
   auto take = [&](uint32_t nb) -> uint64_t {  // nb <= 32, never past nbits
     if (!nb) return 0;
     if (pos + nb > nbits) { bad = true; pos = nbits; return 0; }
@@ -386,24 +405,52 @@ __global__ void cpc_decode(const uint8_t *cs, uint64_t cs_len, uint64_t n, float
     if (nb > 32u) { const uint64_t hi = take(nb - 32u); return (hi << 32) | take(32u); }
     return take(nb);
   };
-  uint64_t k = take_wide(kb);
-  const uint32_t r = (uint32_t)take(6);
-  if (r > kb) bad = true;
-  for (uint32_t i = 0; i < m && !bad; i++) {
-    if (i) {
-      uint32_t q = 0;
-      while (q < kEscQ && !bad && take(1)) q++;
-      uint64_t d;
-      if (q == kEscQ) d = take_wide(kb);
-      else d = ((uint64_t)q << r) | take_wide(r);
-      k += d;
-    }
+  // the Rice parameter follows the first key
+  uint32_t r = 0;
+  if (!bad) {
+    pos = kb;
+    r = (uint32_t)take(6);
+    if (r > kb) bad = true;
+  }
+  const uint64_t start = active ? ent[lane] : 0;
+  const uint64_t stop = (k1 < m) ? ent[lane + 1] : nbits;
+  if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
+  auto next = [&](uint32_t i) -> uint64_t {  // delta of key i (the raw key for i = 0)
+    if (i == 0) { const uint64_t k = take_wide(kb); (void)take(6); return k; }
+    uint32_t q = 0;
+    while (q < kEscQ && !bad && take(1)) q++;
+    if (q == kEscQ) return take_wide(kb);
+    return ((uint64_t)q << r) | take_wide(r);
+  };
+  // pass 1: sum of this lane's deltas
+  uint64_t sum = 0;
+  if (active && !bad) {
+    pos = start;
+    for (uint32_t i = k0; i < k1 && !bad; i++) sum += next(i);
+    if (pos != stop) bad = true;
+  }
+  // exclusive prefix of the lane sums
+  uint64_t inc = sum;
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint64_t o = __shfl_up(inc, d, kWave);
+    if ((int)lane >= d) inc += o;
+  }
+  const bool any_bad = __ballot(bad) != 0;
+  if (any_bad) {
+    if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    return;
+  }
+  // pass 2: keys and coordinates
+  if (!active) return;
+  uint64_t k = inc - sum;
+  pos = start;
+  for (uint32_t i = k0; i < k1; i++) {
+    k += next(i);
     const uint32_t px = compact3(k >> 2), py = compact3(k >> 1), pz = compact3(k);
     ox[base + i] = (float)fma((double)(int32_t)px, step[0], (double)mn[0]);
     oy[base + i] = (float)fma((double)(int32_t)py, step[1], (double)mn[1]);
     oz[base + i] = (float)fma((double)(int32_t)pz, step[2], (double)mn[2]);
   }
-  if (bad) atomicCAS(status, 0, SZNB_ECORRUPT);
 }
 
 // Container (96-byte header): "SZMD" u16 1 u8 mode u8 nf u64 n u32 seg

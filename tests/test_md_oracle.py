@@ -161,3 +161,26 @@ def test_container_layout():
     assert offs[0] == md.MD_HDR and all(o % 8 == 0 for o in offs[:4]) and offs[4:] == [0, 0]
     assert blob[offs[0]:offs[0] + 4] == b"SZCP"
     assert all(blob[o:o + 4] == b"SZNB" for o in offs[1:4])
+
+
+def test_cpc_entry_points_start_codes():
+    # every stored entry point is where the code of key 256 c begins: an
+    # independent bit reader started there decodes the right delta
+    rng = np.random.default_rng(12)
+    keys = np.cumsum(rng.geometric(1 / 3000.0, size=1000)).astype(np.uint64)
+    kb = 40
+    words, nbits, ent = md.cpc_encode_segment(keys, kb, with_entries=True)
+    bits = "".join(format(int(w), "032b") for w in words)[:nbits]
+    r = int(bits[kb:kb + 6], 2)
+    assert list(ent[:1]) == [0] and len(ent) == 4
+    for c in range(1, len(ent)):
+        p = int(ent[c])
+        q = 0
+        while q < md.CPC_ESC_Q and bits[p] == "1":
+            q += 1
+            p += 1
+        if q == md.CPC_ESC_Q:
+            d = int(bits[p:p + kb], 2)
+        else:
+            d = (q << r) | (int(bits[p + 1:p + 1 + r], 2) if r else 0)
+        assert d == int(keys[256 * c] - keys[256 * c - 1])
