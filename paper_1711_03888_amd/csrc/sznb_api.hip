@@ -32,7 +32,7 @@ __global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
 __global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int, const uint32_t *);
-__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *);
+__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t);
 
 template <int E>
 __global__ void k_features(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, float *, uint64_t *,
@@ -728,7 +728,7 @@ static DLayout decompress_layout(int nf, const uint64_t *n) {
     L.nbmax[f] = (n[f] + 1023) / 1024;
     L.boff[f] = o; o = al256(o + 4ull * L.nbmax[f]);
     L.order[f] = o; o = al256(o + 4ull * L.nbmax[f]);
-    L.lut[f] = o; o = al256(o + 4ull * 3 * (1u << kLutBits));
+    L.lut[f] = o; o = al256(o + 4ull * 3 * (2u << kLutBits));  // per predictor: first-code table, small-symbol table
     L.slow[f] = o; o = al256(o + 4ull * 3 * kSlowWords);
     L.syms[f] = o; o = al256(o + 2ull * 3 * kNSyms);
   }
@@ -741,7 +741,7 @@ struct DLaunch {
   int nf = 0;
   uint8_t *ws = nullptr;
   DLayout L;
-  uint32_t smax = 1024, symcap = 0, dw = 1;
+  uint32_t smax = 1024, symcap = 0, dw = 1, lut_words = 1u << kLutBits;
   size_t lds = 0;
   int grid = 1;
 };
@@ -797,19 +797,26 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
       if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
     }
   }
+  // the multi-symbol table pays when every codebook is small (short codes,
+  // symbols near 32768); otherwise its LDS is better spent on waves
+  const uint32_t lut_words = nsym_max <= 4096 ? (2u << kLutBits) : (1u << kLutBits);
   const size_t lds_cu = (dv->lds_per_block ? dv->lds_per_block : 65536) - 1024;
-  const size_t tables = 4ull * (1u << kLutBits) + 4ull * 64 + 8ull * 32;
-  uint32_t symcap = nsym_max;
+  const size_t tables = 4ull * lut_words + 4ull * 64 + 8ull * 32;
   const size_t per_wave = 2ull * (smax + smax / 32);
-  if (tables + ((2ull * symcap + 15) & ~15ull) + per_wave > lds_cu) symcap = 0;
-  const size_t symb = (2ull * symcap + 15) & ~15ull;
-  uint32_t dw = 1, best = 0;
-  for (uint32_t cand = 1; cand <= 16; cand++) {
-    const size_t need = tables + symb + cand * per_wave;
-    if (need > lds_cu) break;
-    const uint32_t waves = cand * (uint32_t)(lds_cu / need);
-    if (waves >= best) { best = waves; dw = cand; }
+  // canonical symbols in LDS (long codes resolve without a global read) or
+  // in global memory (more waves per CU): the layout with more resident
+  // waves wins, LDS symbols on a tie
+  uint32_t symcap = 0, dw = 1, best = 0;
+  for (uint32_t cap : {nsym_max, 0u}) {
+    const size_t symb = (2ull * cap + 15) & ~15ull;
+    for (uint32_t cand = 1; cand <= 16; cand++) {
+      const size_t need = tables + symb + cand * per_wave;
+      if (need > lds_cu) break;
+      const uint32_t waves = cand * (uint32_t)(lds_cu / need);
+      if (waves > best || (waves == best && cap == symcap)) { best = waves; dw = cand; symcap = cap; }
+    }
   }
+  const size_t symb = (2ull * symcap + 15) & ~15ull;
   const size_t lds = tables + symb + dw * per_wave;
   if (lds > 65536) {
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(d_decode), hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -819,6 +826,7 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
   P.nf = nf;
   P.ws = ws;
   P.L = L;
+  P.lut_words = lut_words;
   P.smax = smax;
   P.symcap = symcap;
   P.dw = dw;
@@ -839,7 +847,7 @@ static int decompress_run(const DLaunch &P, hipStream_t stream) {
   SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket, nconst);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf, nconst);
   SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.dw, P.smax,
-              P.symcap, ticket);
+              P.symcap, ticket, P.lut_words);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D,
     int bad = 0;
     st->status = 0;
     st->is_const = 0;
+    st->multi = 0;
     if (df.in_len < (uint64_t)kHdr || rd32(in, H_MAGIC) != kMagic || rd16(in, H_VERSION) != 1) bad = 1;
     uint32_t policy = 0, flags = 0, S = 0, nb = 0;
     uint64_t n = 0, total = 0;
@@ -192,8 +193,17 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
   const uint64_t so = bo + 4ull * ml;
   for (uint32_t i = t; i < ns; i += kThreads) syms[i] = rd16(in, so + 2ull * i);
   __syncthreads();
-  uint32_t *lut = df.lut + (uint64_t)k * (1u << kLutBits);
-  for (uint32_t e = t; e < (1u << kLutBits); e += kThreads) {
+  // first code of every 12-bit window: its symbol and length, then how many
+  // whole codes the window holds and their total length (bits 24-27 and
+  // 28-31: the counting pass steps over all of them at once)
+  __shared__ uint8_t s_len[1u << kLutBits];  // length of a code within the window, 0 if none
+  __shared__ uint16_t s_sym[1u << kLutBits];  // its symbol
+  __shared__ uint32_t s_nmulti;
+  if (t == 0) s_nmulti = 0;
+  uint32_t *lut = df.lut + (uint64_t)k * (2u << kLutBits);
+  uint32_t *lut2 = lut + (1u << kLutBits);
+  uint32_t ents[(1u << kLutBits) / kThreads];
+  for (uint32_t e = t, j = 0; e < (1u << kLutBits); e += kThreads, j++) {
     const uint64_t win = (uint64_t)e << (32 - kLutBits);
     uint32_t len = 1;
     for (uint32_t l = 1; l <= ml; l++) len += s_limit[l] <= win;
@@ -204,8 +214,41 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
       const uint32_t code = (uint32_t)(win >> (32 - len));
       ent = (uint32_t)syms[s_base[len] + (code - s_first[len])] | (len << 16);
     }
-    lut[e] = ent;
+    ents[j] = ent;
+    s_len[e] = (uint8_t)((ent & (kLutInvalid | kLutLong)) ? 0u : len);
+    s_sym[e] = (uint16_t)(ent & 0xffffu);
   }
+  __syncthreads();
+  // second table: up to three leading codes of the window whose symbols are
+  // within 127 of 32768, as signed bytes, their count and total length
+  for (uint32_t e = t, j = 0; e < (1u << kLutBits); e += kThreads, j++) {
+    uint32_t pos = 0, cnt = 0, n2 = 0, l2 = 0, d3 = 0;
+    bool small = true;
+    for (;;) {
+      // code at bit pos of the window (bits past the window read as zero;
+      // a code is counted only if it ends inside the window)
+      const uint32_t w = (e << pos) & ((1u << kLutBits) - 1u);
+      const uint32_t l = s_len[w];
+      if (!l || pos + l > (uint32_t)kLutBits) break;
+      const int32_t dv = (int32_t)s_sym[w] - kRadius;
+      if (small && n2 < 3u && dv >= -128 && dv <= 127) {
+        d3 |= ((uint32_t)dv & 255u) << (8 * n2);
+        n2++;
+        l2 = pos + l;
+      } else {
+        small = false;
+      }
+      pos += l;
+      cnt++;
+    }
+    lut[e] = ents[j] | (cnt << 24) | (pos << 28);
+    lut2[e] = d3 | (n2 << 24) | (l2 << 26);
+    if (n2 >= 2u) atomicAdd(&s_nmulti, 1u);
+  }
+  __syncthreads();
+  // the multi-symbol step pays for its extra lookup when at least a quarter
+  // of the windows (of the code's own probability mass) offer one
+  if (t == 0 && s_nmulti >= (1u << kLutBits) / 4) atomicOr(&st->multi, 1u << k);
   uint32_t *slow = df.slow + (uint64_t)k * kSlowWords;
   if (t < 32) {
     slow[t] = s_first[t];
@@ -272,6 +315,8 @@ __global__ void d_const(const DField *__restrict__ D, int nf, const uint32_t *nc
 
 struct DecTab {
   const uint32_t *lut;     // LDS: 4096 first-level entries
+  const uint32_t *lut2;    // LDS: 4096 small-symbol entries
+  bool multi;              // use them
   const uint32_t *first;   // LDS: first canonical code of each length
   const uint32_t *base;    // LDS: canonical index of that code
   const uint64_t *limit;   // LDS: end of the left-justified code range of each length
@@ -322,7 +367,7 @@ __device__ inline uint32_t decode_len(const DecTab &T, uint32_t win) {
 // symbol | length << 16 (plus the invalid flag for a pattern that is no codeword)
 __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
   const uint32_t e = T.lut[win >> (32 - kLutBits)];
-  if (!(e & kLutLong)) return e;
+  if (!(e & kLutLong)) return e & 0x00ffffffu;
   uint32_t len = (e >> 16) & 31u;
   while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
   if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
@@ -383,7 +428,16 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
     BitReader br;
     br_init(br, wp, cw, pos);
     while (pos < e) {
-      const uint32_t ln = decode_len(T, br_peek(br));
+      const uint32_t win = br_peek(br);
+      const uint32_t ent = T.lut[win >> (32 - kLutBits)];
+      const uint32_t mc = (ent >> 24) & 15u, ml = ent >> 28;
+      if (mc >= 2u && pos + ml <= e) {  // several whole codes, all starting before e
+        pos += ml;
+        br_skip(br, ml);
+        cnt += mc;
+        continue;
+      }
+      const uint32_t ln = decode_len(T, win);
       pos += ln;
       br_skip(br, ln);
       cnt++;
@@ -401,14 +455,38 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
     if (p < e && i < len) {
       BitReader br;
       br_init(br, wp, cw, p);
-      while (p < e && i < len) {
-        const uint32_t r = decode_sym(T, br_peek(br));
-        const uint32_t ln = (r >> 16) & 31u;
-        if (r & kLutInvalid) invalid = 1;
-        q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
-        p += ln;
-        br_skip(br, ln);
-        i++;
+      if (T.multi) {
+        while (p < e && i < len) {
+          const uint32_t win = br_peek(br);
+          const uint32_t m = T.lut2[win >> (32 - kLutBits)];
+          const uint32_t n2 = (m >> 24) & 3u, l2 = (m >> 26) & 15u;
+          if (n2 >= 2u && p + l2 <= e && i + n2 <= len) {  // two or three small symbols at once
+            q16[qaddr(i)] = (uint16_t)(kRadius + (int32_t)(int8_t)(m & 255u));
+            q16[qaddr(i + 1)] = (uint16_t)(kRadius + (int32_t)(int8_t)((m >> 8) & 255u));
+            if (n2 == 3u) q16[qaddr(i + 2)] = (uint16_t)(kRadius + (int32_t)(int8_t)((m >> 16) & 255u));
+            p += l2;
+            br_skip(br, l2);
+            i += n2;
+            continue;
+          }
+          const uint32_t r = decode_sym(T, win);
+          const uint32_t ln = (r >> 16) & 31u;
+          if (r & kLutInvalid) invalid = 1;
+          q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
+          p += ln;
+          br_skip(br, ln);
+          i++;
+        }
+      } else {
+        while (p < e && i < len) {
+          const uint32_t r = decode_sym(T, br_peek(br));
+          const uint32_t ln = (r >> 16) & 31u;
+          if (r & kLutInvalid) invalid = 1;
+          q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
+          p += ln;
+          br_skip(br, ln);
+          i++;
+        }
       }
     }
   }
@@ -456,14 +534,15 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
   __builtin_amdgcn_wave_barrier();
 }
 
-// dw waves per workgroup.  Dynamic LDS: lut (4096 words) | first, base (32
+// dw waves per workgroup.  Dynamic LDS: lut (4096 words), lut2 (4096 words
+// when some codebook is small enough to use it) | first, base (32
 // words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
 // code regions of 2 (smax + smax/32) bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
-                         uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket) {
+                         uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket, uint32_t lut_words) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
-  uint32_t *s_first = s_lut + (1u << kLutBits);
+  uint32_t *s_first = s_lut + lut_words;
   uint32_t *s_base = s_first + 32;
   uint64_t *s_limit = reinterpret_cast<uint64_t *>(s_base + 32);
   uint16_t *s_syms = reinterpret_cast<uint16_t *>(s_limit + 32);
@@ -492,8 +571,8 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     const DState *st = df.st;
     if (pair != cur) {
       __syncthreads();
-      const uint32_t *gl = df.lut + (uint64_t)k * (1u << kLutBits);
-      for (uint32_t i = t; i < (1u << kLutBits); i += blockDim.x) s_lut[i] = gl[i];
+      const uint32_t *gl = df.lut + (uint64_t)k * (2u << kLutBits);
+      for (uint32_t i = t; i < lut_words; i += blockDim.x) s_lut[i] = gl[i];
       const uint32_t *gs = df.slow + (uint64_t)k * kSlowWords;
       for (uint32_t i = t; i < 32u; i += blockDim.x) {
         s_first[i] = gs[i];
@@ -511,6 +590,8 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     }
     DecTab T2;
     T2.lut = s_lut;
+    T2.lut2 = s_lut + (1u << kLutBits);
+    T2.multi = lut_words > (1u << kLutBits) && ((st->multi >> k) & 1u);
     T2.first = s_first;
     T2.base = s_base;
     T2.limit = s_limit;

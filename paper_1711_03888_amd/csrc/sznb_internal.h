@@ -138,7 +138,8 @@ __host__ __device__ inline int slot_pred(int policy, int s) { return policy >= 2
 struct alignas(64) DState {
   int32_t status;
   uint32_t is_const;
-  uint32_t policy, S, nblocks, pad1;
+  uint32_t policy, S, nblocks;
+  uint32_t multi;         // bit k: predictor k's code decodes two or three small symbols per lookup often
   uint64_t n;
   float mn;
   uint32_t pad2;
@@ -160,7 +161,7 @@ struct alignas(16) DField {
   DState *st;
   uint32_t *boff;         // payload word offset of every block
   uint32_t *order;        // block ids grouped by predictor
-  uint32_t *lut;          // 3 x 4096 first-level decode entries
+  uint32_t *lut;          // 3 x (4096 first-code entries + 4096 small-symbol entries)
   uint32_t *slow;         // 3 x (32 first + 32 base + 64 limit words)
   uint16_t *syms;         // 3 x 65536 canonical symbols
 };
