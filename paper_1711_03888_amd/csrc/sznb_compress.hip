@@ -291,6 +291,8 @@ __device__ inline int32_t residual_at(const int32_t (&d)[E], const int32_t (&pv)
   return (int32_t)(b0 - (a1 - a2));
 }
 
+constexpr int kClsCopies = 8, kClsStride = 100;  // class-counter copies of the trial
+
 // Exhaustive trial of one block: the two-part size estimate of LV, LCF and
 // QCF residuals (classes of res_class, 2^-16 bit units), argmin with ties to
 // the lowest predictor.  Leaves the costs in s_cost and the choice in
@@ -300,9 +302,13 @@ __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3]
                                    const uint32_t *__restrict__ logt, uint32_t *s_cls, uint32_t *s_extra,
                                    unsigned long long *s_cost, int *s_pred) {
   const int t = threadIdx.x;
-  if (t < 3 * kNClass) s_cls[t] = 0;
+  // kClsCopies copies of the 99 counters, lane l of a wave on copy l mod 8:
+  // a class hit by a whole wave costs 8 serialised updates, not 64 (the
+  // copies' strides put one class of all copies on distinct banks)
+  for (int i = t; i < kClsCopies * kClsStride; i += kThreads) s_cls[i] = 0;
   if (t < 3) { s_extra[t] = 0; s_cost[t] = 0; }
   __syncthreads();
+  uint32_t *my = s_cls + (t & (kClsCopies - 1)) * kClsStride;
   uint32_t ex[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int e = 0; e < E; e++) {
@@ -311,7 +317,7 @@ __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3]
       for (int k = 0; k < 3; k++) {
         uint32_t xb;
         uint32_t cl = res_class(residual_at<E>(d, pv, e, k), xb);
-        atomicAdd(&s_cls[k * kNClass + cl], 1u);
+        atomicAdd(&my[k * kNClass + cl], 1u);
         ex[k] += xb;
       }
     }
@@ -323,7 +329,8 @@ __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3]
   }
   __syncthreads();
   if (t < 3 * kNClass) {
-    uint32_t n_c = s_cls[t];
+    uint32_t n_c = 0;
+    for (int j = 0; j < kClsCopies; j++) n_c += s_cls[j * kClsStride + t];
     if (n_c) atomicAdd(&s_cost[t / kNClass], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]));
   }
   __syncthreads();
@@ -497,7 +504,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     __syncthreads();
   }
   __shared__ int32_t s_tail[3 * kThreads];
-  __shared__ uint32_t s_cls[3 * kNClass];
+  __shared__ uint32_t s_cls[kClsCopies * kClsStride];
   __shared__ uint32_t s_extra[3];
   __shared__ unsigned long long s_cost[3];
   __shared__ int32_t s_p0;
@@ -623,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
                                                        uint64_t *cost, uint8_t *label) {
   constexpr int S = E * kThreads;
   __shared__ int32_t s_tail[3 * kThreads];
-  __shared__ uint32_t s_cls[3 * kNClass];
+  __shared__ uint32_t s_cls[kClsCopies * kClsStride];
   __shared__ uint32_t s_extra[3];
   __shared__ unsigned long long s_cost[3];
   __shared__ int32_t s_p0;
