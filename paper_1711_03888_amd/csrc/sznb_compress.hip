@@ -1044,7 +1044,7 @@ __global__ __launch_bounds__(kThreads) void k_books(const CField *__restrict__ F
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagPre = 2ull << 62, kValMask = (1ull << 62) - 1;
 
 template <int E>
-__global__ __launch_bounds__(kThreads) void k_pack(const CField *__restrict__ F, int nf,
+__global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__ F, int nf,
                                                    const uint64_t *__restrict__ fb0, uint64_t total, GCtl *gc) {
   constexpr int S = E * kThreads;
   constexpr int CWMAX = S * kLMax / 32 + 16;  // code words plus the skip table
