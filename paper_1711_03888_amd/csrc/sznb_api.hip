@@ -327,8 +327,7 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params
   GCtl *gc = reinterpret_cast<GCtl *>(P.ws + P.L.gctl);
   uint64_t *lb = reinterpret_cast<uint64_t *>(P.ws + P.L.lbflag);
   const uint64_t tb = P.total_blocks;
-  const int ginit = 1024;
-  SZNB_LAUNCH("k_init", k_init, dim3(ginit), dim3(kThreads), 0, s, F, P.nf, gc, lb, tb);
+  SZNB_LAUNCH("k_init", k_init, dim3(16, (unsigned)std::min(P.nf, 65535)), dim3(kThreads), 0, s, F, P.nf, gc, lb, tb);
   int gper = (int)std::min<uint64_t>((uint64_t)dv->cus * g_wg_per_cu, std::max<uint64_t>(tb, 1));
   if (gper > 8) gper &= ~7;  // multiple of the XCD count keeps a block on one XCD across passes
   if (tb) SZNB_LAUNCH("k_range", k_range, dim3(gper), dim3(kThreads), 0, s, F, P.nf, fb0, tb);

@@ -18,26 +18,34 @@ namespace sznb {
 
 // ------------------------------------------------------------------ init
 
+// Grid (kInitParts, min(nf, 65535)): workgroup (x, y) clears part x of the
+// histograms of fields y, y + gridDim.y, ...; part 0 also resets their
+// state; every workgroup clears its share of the look-back words.
+constexpr int kInitParts = 16;
 __global__ void k_init(const CField *__restrict__ F, int nf, GCtl *gc, uint64_t *lbflag_all,
                        uint64_t total_blocks) {
-  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t wg = (uint64_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const uint64_t tid = wg * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * gridDim.y * blockDim.x;
   if (tid == 0) gc->ticket = 0;
-  for (uint64_t i = tid; i < (uint64_t)nf; i += stride) {
-    FState *s = F[i].st;
-    s->status = 0;
-    s->is_const = 0;
-    s->blocks_done = 0;
-    s->payload_words = 0;
-    s->off_payload = 0;
-    for (int k = 0; k < 3; k++) { s->nsym[k] = 0; s->maxlen[k] = 0; }
-  }
   for (uint64_t g = tid; g < total_blocks; g += stride) lbflag_all[g] = 0;
-  // code histograms start from zero on every call
-  for (int f = 0; f < nf; f++) {
+  for (int f = blockIdx.y; f < nf; f += gridDim.y) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      FState *s = F[f].st;
+      s->status = 0;
+      s->is_const = 0;
+      s->blocks_done = 0;
+      s->fallbacks = 0;
+      s->payload_words = 0;
+      s->off_payload = 0;
+      for (int k = 0; k < 3; k++) { s->nsym[k] = 0; s->maxlen[k] = 0; }
+    }
+    // code histograms start from zero on every call
     uint4 *h = reinterpret_cast<uint4 *>(F[f].hist);
     const uint64_t n4 = (uint64_t)F[f].nhist * kNSyms / 4;
-    for (uint64_t i = tid; i < n4; i += stride) h[i] = make_uint4(0u, 0u, 0u, 0u);
+    const uint64_t part = (n4 + kInitParts - 1) / kInitParts;
+    const uint64_t lo = part * blockIdx.x, hi = min(n4, lo + part);
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) h[i] = make_uint4(0u, 0u, 0u, 0u);
   }
 }
 

@@ -131,3 +131,15 @@ def test_adam_vs_oracle():
         sznb.mlp_adam(wd, md, vd, _dev(g), step, 1e-2)
         wr, m, v = mlp.adam(wr, m, v, g.astype(np.float64), step, 1e-2)
     assert np.abs(wd.cpu().numpy() - wr).max() <= 1e-5
+
+
+def test_fallback_count_restarts_each_call():
+    # the same workspace twice: the counter reports this call's fallbacks only
+    rng = np.random.default_rng(29)
+    sznb.set_selector(rng.normal(0, 0.5, mlp.NPARAM).astype(np.float32), float("inf"))
+    x = _dev(np.ascontiguousarray(datagen.random_walk(6 * 4096 + 5, seed=13), np.float32))
+    mode = sznb.PRED_LEARNED | sznb.EB_REL
+    c = sznb.compress_batch_async([x], 1e-4, mode)
+    assert sznb.compress_fallbacks(c.ws, 1) == [7]
+    c2 = sznb.compress_batch_async([x], 1e-4, mode, ws=c.ws, outs=c.bufs, lens=c.lens)
+    assert sznb.compress_fallbacks(c2.ws, 1) == [7]
