@@ -21,7 +21,7 @@ template <int E, bool kLearn>
 __global__ void k_quant(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, uint32_t,
                         const uint32_t *, uint32_t *, const float *);
 __global__ void k_hmerge(const CField *, uint32_t, uint32_t, const uint32_t *, const uint32_t *);
-__global__ void k_huff(const CField *, int, uint8_t *, uint64_t);
+__global__ void k_huff(const CField *, int, uint8_t *, uint64_t, uint32_t, GCtl *);
 __global__ void k_books(const CField *);
 template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, uint64_t, GCtl *);
 __global__ void k_final(const CField *, int);
@@ -158,7 +158,8 @@ struct CLayout {
   uint64_t gctl, states, fields, fb0, blkstat, lbflag, perfield_base, hscratch, qmeta, slabs, total;
   std::vector<uint64_t> hist, enc, book, nblocks, gblock0, nhist;
   uint64_t total_blocks;
-  int nslots;         // Huffman workgroups: (field, predictor) pairs, at most 64
+  int nslots;         // Huffman workgroups, at most 64
+  int hvar;           // Huffman variants per (field, predictor) pair
   uint32_t qslots;    // histogram windows per quantization workgroup
   uint64_t qmax;      // quantization workgroups the slabs are sized for
 };
@@ -189,7 +190,10 @@ static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) 
     L.enc[f] = o; o = al256(o + 4ull * kNSyms * L.nhist[f]);
     L.book[f] = o; o = al256(o + 4ull * kBookWords * L.nhist[f]);
   }
-  L.nslots = npairs < 64 ? (npairs > 0 ? npairs : 1) : 64;
+  // Huffman workgroups: with few fields, several per (field, predictor)
+  // pair, each starting from another number of weight halvings
+  L.hvar = 3 * nf <= kHuffSlots / 2 ? std::min(4, kHuffSlots / (3 * nf)) : 1;
+  L.nslots = L.hvar > 1 ? 3 * nf * L.hvar : std::min(std::max(npairs, 1), kHuffSlots);
   L.hscratch = o; o = al256(o + hscratch_bytes_host() * (uint64_t)L.nslots);
   // quantization plan: per workgroup its first visit and first field, per
   // field its first and last workgroup; one histogram slab per visit
@@ -334,7 +338,8 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params
   SZNB_LAUNCH("k_params", k_params, dim3(P.nf), dim3(kThreads), 0, s, F);
   if (params_only) return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
   if (tb) launch_E(true, P, s, gper);
-  SZNB_LAUNCH("k_huff", k_huff, dim3(P.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host());
+  SZNB_LAUNCH("k_huff", k_huff, dim3(P.L.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host(),
+              (uint32_t)P.L.hvar, gc);
   SZNB_LAUNCH("k_books", k_books, dim3(P.nf), dim3(kThreads), 0, s, F);
   if (tb) launch_E(false, P, s, gper);
   SZNB_LAUNCH("k_final", k_final, dim3((P.nf + 63) / 64), dim3(64), 0, s, F, P.nf);

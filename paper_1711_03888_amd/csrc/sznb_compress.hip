@@ -28,6 +28,7 @@ __global__ void k_init(const CField *__restrict__ F, int nf, GCtl *gc, uint64_t 
   const uint64_t tid = wg * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * gridDim.y * blockDim.x;
   if (tid == 0) gc->ticket = 0;
+  if (tid < kHuffSlots) gc->hdone[tid] = 0;
   for (uint64_t g = tid; g < total_blocks; g += stride) lbflag_all[g] = 0;
   for (int f = blockIdx.y; f < nf; f += gridDim.y) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -61,12 +62,12 @@ __global__ __launch_bounds__(kThreads) void k_range(const CField *__restrict__ F
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b << c.log2S;
     const uint32_t len = (uint32_t)min((uint64_t)c.S, c.n - i0);
-    const float *x = c.x + i0;
+    const gptr<const float> x = G(c.x) + i0;
     uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
     for (uint32_t j = 4u * t; j < len; j += 4u * kThreads) {
       float v[4];
       if (j + 4 <= len) {
-        float4 q = *reinterpret_cast<const float4 *>(x + j);
+        const f32x4 q = *reinterpret_cast<gptr<const f32x4>>(x + j);
         v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
       } else {
         for (int e = 0; e < 4; e++) v[e] = j + e < len ? x[j + e] : x[j];
@@ -90,9 +91,10 @@ __global__ __launch_bounds__(kThreads) void k_range(const CField *__restrict__ F
         mx = max(mx, s_mx[i]);
         bad |= s_bad[i];
       }
-      c.blkstat[3 * b + 0] = mn;
-      c.blkstat[3 * b + 1] = mx;
-      c.blkstat[3 * b + 2] = bad;
+      const gptr<uint32_t> bs = G(c.blkstat) + 3 * b;
+      bs[0] = mn;
+      bs[1] = mx;
+      bs[2] = bad;
     }
     __syncthreads();
   }
@@ -235,13 +237,13 @@ __device__ inline int32_t lattice_of(float x, float mn, double inv) {
 // This thread's E contiguous values of a block (16-byte loads when the run
 // is whole; the tail of a ragged block reads as mn).
 template <int E>
-__device__ inline void load_raw(const float *x_block, uint32_t len, float mn, float (&v)[E]) {
+__device__ inline void load_raw(gptr<const float> x_block, uint32_t len, float mn, float (&v)[E]) {
   const int t = threadIdx.x;
-  const float *x = x_block + (uint64_t)t * E;
+  const gptr<const float> x = x_block + (uint64_t)t * E;
   if ((uint32_t)(t + 1) * E <= len) {
 #pragma unroll
     for (int e = 0; e < E; e += 4) {
-      float4 q = *reinterpret_cast<const float4 *>(x + e);
+      const f32x4 q = *reinterpret_cast<gptr<const f32x4>>(x + e);
       v[e] = q.x; v[e + 1] = q.y; v[e + 2] = q.z; v[e + 3] = q.w;
     }
   } else {
@@ -254,11 +256,9 @@ __device__ inline void load_raw(const float *x_block, uint32_t len, float mn, fl
 // (d_j = p_j - p_0), and the three values that precede the thread's run
 // (zero before the block start).
 template <int E>
-__device__ inline void block_d_from_raw(const float (&v)[E], const FState *st, int32_t (&d)[E], int32_t (&pv)[3],
+__device__ inline void block_d_from_raw(const float (&v)[E], float mn, double inv, int32_t (&d)[E], int32_t (&pv)[3],
                                         int32_t *s_tail, int32_t &p0_out, int32_t *s_p0) {
   const int t = threadIdx.x;
-  const float mn = st->mn;
-  const double inv = st->inv;
   int32_t p[E];
 #pragma unroll
   for (int e = 0; e < E; e++) p[e] = lattice_of(v[e], mn, inv);
@@ -277,12 +277,12 @@ __device__ inline void block_d_from_raw(const float (&v)[E], const FState *st, i
 }
 
 template <int E>
-__device__ inline void load_block_d(const CField &c, const FState *st, uint64_t i0, uint32_t len,
+__device__ inline void load_block_d(const CField &c, float mn, double inv, uint64_t i0, uint32_t len,
                                     int32_t (&d)[E], int32_t (&pv)[3], int32_t *s_tail, int32_t &p0_out,
                                     int32_t *s_p0) {
   float v[E];
-  load_raw<E>(c.x + i0, len, st->mn, v);
-  block_d_from_raw<E>(v, st, d, pv, s_tail, p0_out, s_p0);
+  load_raw<E>(G(c.x) + i0, len, mn, v);
+  block_d_from_raw<E>(v, mn, inv, d, pv, s_tail, p0_out, s_p0);
 }
 
 // residual of predictor k at element e given the run d[] and its three
@@ -481,12 +481,15 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
 // Adds v (<= 64) to 16-bit counter idx16 of the LDS window; a counter that
 // wraps hands 65536 to its global histogram bin (and the carry it pushed
 // into its upper neighbour is taken back).
-__device__ inline void win_add(uint32_t *s_win, uint32_t idx16, uint32_t v, uint32_t *gbin) {
+__device__ inline void gadd(gptr<uint32_t> p, uint32_t v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void win_add(uint32_t *s_win, uint32_t idx16, uint32_t v, gptr<uint32_t> gbin) {
   const uint32_t sh = (idx16 & 1u) << 4;
   const uint32_t old = atomicAdd(&s_win[idx16 >> 1], v << sh);
   if (((old >> sh) & 0xffffu) + v > 0xffffu) {
     if (!sh) atomicSub(&s_win[idx16 >> 1], 0x10000u);
-    atomicAdd(gbin, 0x10000u);
+    gadd(gbin, 0x10000u);
   }
 }
 
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
     const uint64_t i0 = (g - c.gblock0) * S;
-    load_raw<E>(c.x + i0, (uint32_t)min((uint64_t)S, c.n - i0), c.st->mn, v);
+    load_raw<E>(G(c.x) + i0, (uint32_t)min((uint64_t)S, c.n - i0), G(c.st)->mn, v);
   };
   float vn[E];
   if (g_begin < g_end) fetch(g_begin, vn);
@@ -551,14 +554,14 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     if (g + 1 < g_end) fetch(g + 1, vn);
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
-    const FState *st = c.st;
+    const gptr<const FState> st = G(static_cast<const FState *>(c.st));
     if (st->status != 0 || st->is_const) continue;
     if (f != cur) { flush(cur); cur = f; }
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
     int32_t d[E], pv[3], p0;
-    block_d_from_raw<E>(v, st, d, pv, s_tail, p0, &s_p0);
+    block_d_from_raw<E>(v, st->mn, st->inv, d, pv, s_tail, p0, &s_p0);
 
     int pred = (int)c.policy;
     if (c.policy >= 2) {
@@ -579,14 +582,14 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
       }
       if (trial) block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
       pred = s_pred;
-      if (t == 0) c.out[c.sec.pred + b] = (uint8_t)pred;
+      if (t == 0) G(c.out)[c.sec.pred + b] = (uint8_t)pred;
     }
-    if (t == 0) reinterpret_cast<int32_t *>(c.out + c.sec.pfirst)[b] = p0;
+    if (t == 0) reinterpret_cast<gptr<int32_t>>(G(c.out) + c.sec.pfirst)[b] = p0;
 
     // code histogram of the chosen predictor
     const int slot = c.policy >= 2 ? pred : 0;
     const QWin qw = qwin_of(nslots, (uint32_t)slot);
-    uint32_t *gh = c.hist + (uint64_t)slot * kNSyms;
+    const gptr<uint32_t> gh = G(c.hist) + (uint64_t)slot * kNSyms;
 #pragma unroll
     for (int e = 0; e < E; e++) {
       const bool valid = (uint32_t)t * E + e < len;
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
         win_add(s_win, qw.off + qw.size / 2, (uint32_t)__popcll(zmask), &gh[kRadius]);
       if (valid && q != (uint32_t)kRadius) {
         if (q - qw.base < qw.size) win_add(s_win, qw.off + (q - qw.base), 1u, &gh[q]);
-        else atomicAdd(&gh[q], 1u);
+        else gadd(gh + q, 1u);
       }
     }
     __syncthreads();
@@ -649,7 +652,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
   for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
-    const FState *st = c.st;
+    const gptr<const FState> st = G(static_cast<const FState *>(c.st));
     if (st->status != 0 || st->is_const) {
       if (t < kNFeat) feat[g * kNFeat + t] = 0.0f;
       if (t < 3) cost[g * 3 + t] = 0;
@@ -660,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
     int32_t d[E], pv[3], p0;
-    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
+    load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
     block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
     block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
     if (t < kNFeat) feat[g * kNFeat + t] = s_feat[t];
@@ -684,6 +687,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
 
 constexpr int kHT = 1024;
 constexpr int kHW = kHT / kWave;
+constexpr int kStage = 8192;  // largest merge batch ordered in LDS
 
 struct HScratch {
   uint16_t *a_sym; uint32_t *a_f;        // present symbols in symbol order
@@ -798,17 +802,28 @@ __device__ inline uint32_t count_lt(const uint32_t *a, uint32_t n, uint32_t v) {
   return lo;
 }
 
+// With nvar > 1 the grid is (3 nf) x nvar and variant v of a pair starts
+// from v halvings of the weights (halving h times gives ceil(w / 2^h)); the
+// last variant keeps halving until the lengths fit.  The first variant whose
+// lengths fit is the one the sequential procedure stops at; the last
+// variant of the pair to finish builds the canonical code from its lengths.
 __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int nf, uint8_t *scratch,
-                                              uint64_t slot_bytes) {
+                                              uint64_t slot_bytes, uint32_t nvar, GCtl *gc) {
   __shared__ uint32_t s_cnt[256 * kHW];
   __shared__ uint32_t s_tot[kHW];
   __shared__ uint32_t s_red[kHW];
-  __shared__ uint32_t s_n, s_maxf, s_maxlen, s_niter, s_lp, s_ip, s_ni, s_j, s_cL, s_cI, s_aL, s_done;
+  __shared__ uint32_t s_n, s_maxf, s_maxlen, s_niter, s_lp, s_ip, s_ni, s_aL, s_wsum, s_c1[2], s_c2[2];
+  __shared__ uint32_t s_last, s_win;
+  // one merge batch: the weights of both queues' candidates, then its order
+  __shared__ uint32_t s_stage[kStage], s_seqw[kStage], s_seqid[kStage];
   __shared__ uint32_t s_blc[32], s_first[32], s_base[32];
   const int t = threadIdx.x, w = t / kWave;
   HScratch H = hscratch_at(scratch + (uint64_t)blockIdx.x * slot_bytes);
+  const uint32_t var = nvar > 1 ? blockIdx.x % nvar : 0u;
+  const int pair0 = nvar > 1 ? (int)(blockIdx.x / nvar) : (int)blockIdx.x;
+  const int pstep = nvar > 1 ? 3 * nf : (int)gridDim.x;
 
-  for (int pair = blockIdx.x; pair < 3 * nf; pair += gridDim.x) {
+  for (int pair = pair0; pair < 3 * nf; pair += pstep) {
     const int f = pair / 3, slot = pair % 3;
     const CField &c = F[f];
     FState *st = c.st;
@@ -816,22 +831,45 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
     const int k = slot_pred((int)c.policy, slot);
     uint32_t *hist = c.hist + (uint64_t)slot * kNSyms;
 
-    // 1. present symbols in symbol order
+    // 1. present symbols in symbol order: wave w reads symbols
+    // [4096 w, 4096 w + 4096) in rows of 64, eight rows per round trip,
+    // counts them, then writes them after the counts of the waves before it
     {
-      constexpr int PER = kNSyms / kHT;
+      constexpr int SPW = kNSyms / kHW, RB = 8;
+      const gptr<const uint32_t> hw = G(static_cast<const uint32_t *>(hist)) + (uint32_t)w * SPW + lane_id();
       uint32_t cnt = 0, mf = 0;
-      for (int i = 0; i < PER; i++) { uint32_t v = hist[t * PER + i]; cnt += v != 0; mf = max(mf, v); }
-      uint32_t inc = wave_incl_scan(cnt);
+#pragma unroll 1
+      for (int r = 0; r < SPW / kWave; r += RB) {
+        uint32_t v[RB];
+        const gptr<const uint32_t> hr = hw + r * kWave;
+#pragma unroll
+        for (int i = 0; i < RB; i++) v[i] = hr[i * kWave];
+#pragma unroll
+        for (int i = 0; i < RB; i++) { cnt += v[i] != 0u; mf = max(mf, v[i]); }
+      }
+      cnt = wave_sum(cnt);
       mf = wave_max_u32(mf);
-      if (lane_id() == kWave - 1) { s_tot[w] = inc; s_red[w] = mf; }
+      if (lane_id() == 0) { s_tot[w] = cnt; s_red[w] = mf; }
       __syncthreads();
-      uint32_t pre = 0;
-      for (int i = 0; i < w; i++) pre += s_tot[i];
-      uint32_t o = pre + inc - cnt;
-      for (int i = 0; i < PER; i++) {
-        uint32_t sym = t * PER + i;
-        uint32_t v = hist[sym];
-        if (v) { H.a_sym[o] = (uint16_t)sym; H.a_f[o] = v; o++; }
+      uint32_t o = 0;
+      for (int i = 0; i < w; i++) o += s_tot[i];
+      const uint64_t lt = lanemask_lt();
+#pragma unroll 1
+      for (int r = 0; r < SPW / kWave; r += RB) {
+        uint32_t v[RB];
+        const gptr<const uint32_t> hr = hw + r * kWave;
+#pragma unroll
+        for (int i = 0; i < RB; i++) v[i] = hr[i * kWave];
+#pragma unroll
+        for (int i = 0; i < RB; i++) {
+          const uint64_t m = __ballot(v[i] != 0u);
+          if (v[i]) {
+            const uint32_t pos = o + (uint32_t)__popcll(m & lt);
+            H.a_sym[pos] = (uint16_t)((uint32_t)w * SPW + (uint32_t)(r + i) * kWave + lane_id());
+            H.a_f[pos] = v[i];
+          }
+          o += (uint32_t)__popcll(m);
+        }
       }
       if (t == 0) {
         uint32_t nn = 0, m2 = 0;
@@ -842,17 +880,31 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
     }
     const uint32_t n = s_n;
     if (n == 0) continue;
+    if (var) {
+      for (uint32_t i = t; i < n; i += kHT)
+        H.a_f[i] = (uint32_t)(((uint64_t)H.a_f[i] + (1ull << var) - 1) >> var);
+      __syncthreads();
+    }
 
+    bool built = false;
     for (;;) {
       uint32_t maxlen = 1;
       if (n == 1) {
         if (t == 0) { H.depth[0] = 1; H.l_sym[0][0] = H.a_sym[0]; }
         __syncthreads();
       } else {
-        // 2. leaves sorted by (weight, symbol): stable LSD radix on the weight
+        // 2. leaves sorted by (weight, symbol): stable LSD radix on the
+        // weight, in LDS when the leaves fit (the merge buffers are free
+        // until step 3), and the sorted run stored to l_f[0], l_sym[0]
+        const bool in_lds = n <= (uint32_t)kStage;
+        uint16_t *sy0 = reinterpret_cast<uint16_t *>(s_seqid), *sy1 = sy0 + kStage;
         {
           uint32_t mf = 0;  // weights may have been halved since step 1
-          for (uint32_t i = t; i < n; i += kHT) mf = max(mf, H.a_f[i]);
+          for (uint32_t i = t; i < n; i += kHT) {
+            const uint32_t f = H.a_f[i];
+            mf = max(mf, f);
+            if (in_lds) { s_stage[i] = f; sy0[i] = H.a_sym[i]; }
+          }
           mf = wave_max_u32(mf);
           if (lane_id() == 0) s_red[w] = mf;
           __syncthreads();
@@ -869,63 +921,110 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
           while (mf) { passes++; mf >>= 8; }
           if (passes == 0) passes = 1;
         }
-        const uint32_t *kin = H.a_f;
-        const uint16_t *sin = H.a_sym;
-        int pp = 0;
-        for (int ps = 0; ps < passes; ps++) {
-          wg_split(kin, sin, H.l_f[pp], H.l_sym[pp], nullptr, n, 8 * ps, 8, s_cnt, s_tot);
-          kin = H.l_f[pp];
-          sin = H.l_sym[pp];
-          pp ^= 1;
+        const uint32_t *Lw;
+        const uint16_t *Ls;
+        if (in_lds) {
+          uint32_t *kin = s_stage, *kout = s_seqw;
+          uint16_t *sin = sy0, *sout = sy1;
+          for (int ps = 0; ps < passes; ps++) {
+            wg_split(kin, sin, kout, sout, nullptr, n, 8 * ps, 8, s_cnt, s_tot);
+            uint32_t *tk = kin; kin = kout; kout = tk;
+            uint16_t *ts = sin; sin = sout; sout = ts;
+          }
+          for (uint32_t i = t; i < n; i += kHT) { H.l_f[0][i] = kin[i]; H.l_sym[0][i] = sin[i]; }
+          __syncthreads();
+          Lw = H.l_f[0];
+          Ls = H.l_sym[0];
+        } else {
+          const uint32_t *kin = H.a_f;
+          const uint16_t *sin = H.a_sym;
+          int pp = 0;
+          for (int ps = 0; ps < passes; ps++) {
+            wg_split(kin, sin, H.l_f[pp], H.l_sym[pp], nullptr, n, 8 * ps, 8, s_cnt, s_tot);
+            kin = H.l_f[pp];
+            sin = H.l_sym[pp];
+            pp ^= 1;
+          }
+          Lw = kin;
+          Ls = sin;
         }
-        const uint32_t *Lw = kin;
-        const uint16_t *Ls = sin;
 
-        // 3. batched two-queue merge
+        // 3. batched two-queue merge.  Per batch: the weight s of the next
+        // merged node from the heads of both queues; the counts cL, cI of
+        // leaves and merged nodes of weight <= s (two rounds of samples of
+        // each sorted queue, half of the workgroup per queue); the merged
+        // order of those nodes by rank search, in LDS when the batch fits.
         if (t == 0) { s_lp = 0; s_ip = 0; s_ni = 0; s_niter = 0; }
         __syncthreads();
         for (;;) {
+          const uint32_t lp = s_lp, ip = s_ip, ni = s_ni;
+          if ((n - lp) + (ni - ip) <= 1) break;
           if (t == 0) {
-            const uint32_t lp = s_lp, ip = s_ip, ni = s_ni;
-            const uint32_t rem = (n - lp) + (ni - ip);
-            if (rem <= 1) {
-              s_done = 1;
-            } else {
-              s_done = 0;
-              uint32_t a = lp, bq = ip, wsum = 0;
-              for (int q = 0; q < 2; q++) {
-                bool leaf = a < n && (bq >= ni || Lw[a] <= H.iw[bq]);
-                if (leaf) wsum += Lw[a++]; else wsum += H.iw[bq++];
-              }
-              s_cL = count_le(Lw + lp, n - lp, wsum);
-              s_cI = count_le(H.iw + ip, ni - ip, wsum);
-              s_j = (s_cL + s_cI) / 2;
-              s_aL = 0;
-            }
+            const uint32_t x0 = lp < n ? Lw[lp] : ~0u, x1 = lp + 1 < n ? Lw[lp + 1] : ~0u;
+            const uint32_t y0 = ip < ni ? H.iw[ip] : ~0u, y1 = ip + 1 < ni ? H.iw[ip + 1] : ~0u;
+            s_wsum = min(x0, y0) + (x0 <= y0 ? min(x1, y0) : min(x0, y1));
+            s_c1[0] = 0; s_c1[1] = 0; s_c2[0] = 0; s_c2[1] = 0;
           }
           __syncthreads();
-          if (s_done) break;
-          const uint32_t lp = s_lp, ip = s_ip, ni = s_ni, cL = s_cL, cI = s_cI, j = s_j;
+          const uint32_t wsum = s_wsum;
+          const uint32_t q = (uint32_t)t / (kHT / 2), tq = (uint32_t)t % (kHT / 2);
+          const uint32_t *qa = q ? H.iw + ip : Lw + lp;
+          const uint32_t qlen = q ? ni - ip : n - lp;
+          const uint32_t stp = (qlen + kHT / 2 - 1) / (kHT / 2);
+          {
+            const bool le = (uint64_t)tq * stp < qlen && qa[tq * stp] <= wsum;
+            const uint32_t c = (uint32_t)__popcll(__ballot(le));
+            if (lane_id() == 0 && c) atomicAdd(&s_c1[q], c);
+          }
+          __syncthreads();
+          const uint32_t c1 = s_c1[q];
+          {
+            // the count lies in ((c1 - 1) stp, c1 stp]
+            const uint32_t o = (c1 - 1) * stp + 1 + tq;
+            const bool le = c1 && tq + 1 < stp && o < qlen && qa[o] <= wsum;
+            const uint32_t c = (uint32_t)__popcll(__ballot(le));
+            if (lane_id() == 0 && c) atomicAdd(&s_c2[q], c);
+          }
+          __syncthreads();
+          const uint32_t cL = s_c1[0] ? (s_c1[0] - 1) * ((n - lp + kHT / 2 - 1) / (kHT / 2)) + 1 + s_c2[0] : 0u;
+          const uint32_t cI = s_c1[1] ? (s_c1[1] - 1) * ((ni - ip + kHT / 2 - 1) / (kHT / 2)) + 1 + s_c2[1] : 0u;
+          const uint32_t j = (cL + cI) / 2;
+          const bool staged = cL + cI <= (uint32_t)kStage;
+          if (t == 0) s_aL = 0;
+          if (staged) {
+            for (uint32_t e = t; e < cL + cI; e += kHT) s_stage[e] = e < cL ? Lw[lp + e] : H.iw[ip + e - cL];
+          }
+          __syncthreads();
+          uint32_t aL = 0;
           for (uint32_t e = t; e < cL + cI; e += kHT) {
             uint32_t wv, id, pos;
             if (e < cL) {
-              wv = Lw[lp + e];
-              pos = e + count_lt(H.iw + ip, cI, wv);
+              wv = staged ? s_stage[e] : Lw[lp + e];
+              pos = e + (staged ? count_lt(s_stage + cL, cI, wv) : count_lt(H.iw + ip, cI, wv));
               id = lp + e;
-              if (pos < 2 * j) atomicAdd(&s_aL, 1u);
+              aL += pos < 2 * j;
             } else {
               const uint32_t kk = e - cL;
-              wv = H.iw[ip + kk];
-              pos = kk + count_le(Lw + lp, cL, wv);
+              wv = staged ? s_stage[e] : H.iw[ip + kk];
+              pos = kk + (staged ? count_le(s_stage, cL, wv) : count_le(Lw + lp, cL, wv));
               id = n + ip + kk;
             }
-            if (pos < 2 * j) { H.seqw[pos] = wv; H.seqid[pos] = id; }
+            if (pos < 2 * j) {
+              if (staged) { s_seqw[pos] = wv; s_seqid[pos] = id; }
+              else { H.seqw[pos] = wv; H.seqid[pos] = id; }
+            }
           }
+          aL = wave_sum(aL);
+          if (lane_id() == 0 && aL) atomicAdd(&s_aL, aL);
           __syncthreads();
           for (uint32_t i = t; i < j; i += kHT) {
-            H.iw[ni + i] = H.seqw[2 * i] + H.seqw[2 * i + 1];
-            H.parent[H.seqid[2 * i]] = n + ni + i;
-            H.parent[H.seqid[2 * i + 1]] = n + ni + i;
+            const uint32_t w0 = staged ? s_seqw[2 * i] : H.seqw[2 * i];
+            const uint32_t w1 = staged ? s_seqw[2 * i + 1] : H.seqw[2 * i + 1];
+            const uint32_t i0 = staged ? s_seqid[2 * i] : H.seqid[2 * i];
+            const uint32_t i1 = staged ? s_seqid[2 * i + 1] : H.seqid[2 * i + 1];
+            H.iw[ni + i] = w0 + w1;
+            H.parent[i0] = n + ni + i;
+            H.parent[i1] = n + ni + i;
           }
           __syncthreads();
           if (t == 0) {
@@ -965,6 +1064,7 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
         __syncthreads();
         maxlen = s_maxlen;
         if (maxlen > (uint32_t)kLMax) {
+          if (var + 1 < nvar) break;  // a later variant has halved further
           for (uint32_t i = t; i < n; i += kHT) H.a_f[i] = (H.a_f[i] + 1) >> 1;
           __syncthreads();
           continue;
@@ -977,11 +1077,40 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
         if (t == 0) H.len_of[H.a_sym[0]] = 1;
         __syncthreads();
       }
+      built = true;
+      break;
+    }
+    // hand-over between the variants of the pair: each publishes whether
+    // its lengths fit; the last to finish takes the first that fits
+    uint64_t win = blockIdx.x;
+    if (nvar > 1) {
+      __syncthreads();
+      if (t == 0) {
+        __hip_atomic_store(&gc->hres[blockIdx.x], built ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        s_last = atomicAdd(&gc->hdone[pair], 1u) == nvar - 1;
+      }
+      __syncthreads();
+      if (!s_last) continue;
+      __threadfence();
+      if (t == 0) {
+        uint32_t u = 0;
+        while (u + 1 < nvar &&
+               !__hip_atomic_load(&gc->hres[pair * nvar + u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          u++;
+        s_win = pair * nvar + u;
+        gc->hdone[pair] = 0;
+      }
+      __syncthreads();
+      win = s_win;
+    }
+    const uint8_t *len_of = hscratch_at(scratch + win * slot_bytes).len_of;
+    {
       // 5. canonical order = symbols stably sorted by length
-      wg_split(nullptr, H.a_sym, nullptr, H.c_sym, H.len_of, n, 0, 5, s_cnt, s_tot);
+      wg_split(nullptr, H.a_sym, nullptr, H.c_sym, len_of, n, 0, 5, s_cnt, s_tot);
       if (t < 32) s_blc[t] = 0;
       __syncthreads();
-      for (uint32_t i = t; i < n; i += kHT) atomicAdd(&s_blc[H.len_of[H.a_sym[i]]], 1u);
+      for (uint32_t i = t; i < n; i += kHT) atomicAdd(&s_blc[len_of[H.a_sym[i]]], 1u);
       __syncthreads();
       if (t == 0) {
         uint32_t code = 0, idx = 0, ml = 0;
@@ -1001,7 +1130,7 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
       uint16_t *bsym = reinterpret_cast<uint16_t *>(book + 32);
       for (uint32_t i = t; i < n; i += kHT) {
         const uint16_t sym = H.c_sym[i];
-        const uint32_t l = H.len_of[sym];
+        const uint32_t l = len_of[sym];
         const uint32_t code = s_first[l] + (i - s_base[l]);
         enc[sym] = code | (l << 24);
         bsym[i] = sym;
@@ -1009,7 +1138,6 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
       if (t < 32) book[t] = (t >= 1 && t <= kLMax) ? s_blc[t] : 0u;
       if (t == 0) { st->nsym[k] = n; st->maxlen[k] = s_maxlen; }
       __syncthreads();
-      break;
     }
   }
 }
@@ -1072,16 +1200,17 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     if (g >= total) break;
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
-    FState *st = c.st;
+    const gptr<FState> st = G(c.st);
     if (st->status != 0 || st->is_const) continue;
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
     int32_t d[E], pv[3], p0;
-    load_block_d<E>(c, st, i0, len, d, pv, s_tail, p0, &s_p0);
-    const int pred = c.policy >= 2 ? (int)c.out[c.sec.pred + b] : (int)c.policy;
+    load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
+    const gptr<uint8_t> out = G(c.out);
+    const int pred = c.policy >= 2 ? (int)out[c.sec.pred + b] : (int)c.policy;
     const int slot = c.policy >= 2 ? pred : 0;
-    const uint32_t *enc = c.enc + (uint64_t)slot * kNSyms;
+    const gptr<const uint32_t> enc = G(c.enc) + (uint64_t)slot * kNSyms;
 
     uint32_t cw[E];
     int32_t rr[E];
@@ -1120,13 +1249,13 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
       const uint32_t lane = lane_id();
       uint64_t P = 0;
       if (b == 0) {
-        if (lane == 0) st_relaxed_u64(&c.lbflag[0], kFlagPre | words);
+        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[0], kFlagPre | words);
       } else {
-        if (lane == 0) st_relaxed_u64(&c.lbflag[b], kFlagAgg | words);
+        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[b], kFlagAgg | words);
         int64_t base = (int64_t)b - 1;
         for (;;) {
           const int64_t j = base - (int64_t)lane;
-          const uint64_t v = j >= 0 ? ld_relaxed_u64(&c.lbflag[j]) : kFlagPre;
+          const uint64_t v = j >= 0 ? ld_relaxed_u64(&G(c.lbflag)[j]) : kFlagPre;
           const uint64_t pre = __ballot((v >> 62) == 2);
           const uint64_t zero = __ballot(v == 0);
           if (pre) {
@@ -1140,7 +1269,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
           P += wave_sum((unsigned long long)(v & kValMask));
           base -= kWave;
         }
-        if (lane == 0) st_relaxed_u64(&c.lbflag[b], kFlagPre | (P + words));
+        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[b], kFlagPre | (P + words));
       }
       if (lane == 0) s_prefix = P;
     }
@@ -1200,7 +1329,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     const uint64_t P = s_prefix;
     const uint64_t wbase = st->off_payload / 4 + P;
     const bool fits = (wbase + words) * 4 <= c.out_cap;
-    uint32_t *ow = reinterpret_cast<uint32_t *>(c.out);
+    const gptr<uint32_t> ow = reinterpret_cast<gptr<uint32_t>>(out);
     if (fits) {
       for (uint32_t i = t; i < skw + cwn; i += kThreads) ow[wbase + i] = s_words[i];
       if (nesc) {
@@ -1215,8 +1344,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
       st->status = SZNB_ENOSPC;
     }
     if (t == 0) {
-      reinterpret_cast<uint16_t *>(c.out + c.sec.cwords)[b] = (uint16_t)cwn;
-      reinterpret_cast<uint16_t *>(c.out + c.sec.nesc)[b] = (uint16_t)tesc;
+      reinterpret_cast<gptr<uint16_t>>(out + c.sec.cwords)[b] = (uint16_t)cwn;
+      reinterpret_cast<gptr<uint16_t>>(out + c.sec.nesc)[b] = (uint16_t)tesc;
       if (b + 1 == c.nblocks) st->payload_words = P + words;
     }
     __syncthreads();

@@ -14,13 +14,16 @@
 
 namespace sznb {
 
-__device__ inline uint32_t rd32(const uint8_t *p, uint64_t off) {
+template <class P>
+__device__ inline uint32_t rd32(P p, uint64_t off) {
   return (uint32_t)p[off] | ((uint32_t)p[off + 1] << 8) | ((uint32_t)p[off + 2] << 16) | ((uint32_t)p[off + 3] << 24);
 }
-__device__ inline uint64_t rd64(const uint8_t *p, uint64_t off) {
+template <class P>
+__device__ inline uint64_t rd64(P p, uint64_t off) {
   return (uint64_t)rd32(p, off) | ((uint64_t)rd32(p, off + 4) << 32);
 }
-__device__ inline uint16_t rd16(const uint8_t *p, uint64_t off) {
+template <class P>
+__device__ inline uint16_t rd16(P p, uint64_t off) {
   return (uint16_t)(p[off] | (p[off + 1] << 8));
 }
 
@@ -320,18 +323,23 @@ struct DecTab {
   const uint32_t *first;   // LDS: first canonical code of each length
   const uint32_t *base;    // LDS: canonical index of that code
   const uint64_t *limit;   // LDS: end of the left-justified code range of each length
-  const uint16_t *syms;    // LDS when it fits, else global
+  const uint16_t *lsyms;   // LDS symbols, when they fit
+  gptr<const uint16_t> gsyms;  // else the global ones
+  bool syms_lds;
   uint32_t maxlen;
 };
 
 // Per-lane reader of the block's code region: a 64-bit window holding at
-// least 32 unread bits and one prefetched word (zeros past the end).
+// least 32 unread bits and one word read ahead.  Words past the region read
+// as zero: the read-ahead word is fetched at a clamped index and masked when
+// it enters the window, so that the load is only waited for one refill
+// later.
 struct BitReader {
-  const uint32_t *wp;
+  gptr<const uint32_t> wp;
   uint32_t cw, wi, pend, nb;
   uint64_t buf;
 };
-__device__ inline void br_init(BitReader &r, const uint32_t *wp, uint32_t cw, uint32_t pos) {
+__device__ inline void br_init(BitReader &r, gptr<const uint32_t> wp, uint32_t cw, uint32_t pos) {
   r.wp = wp;
   r.cw = cw;
   const uint32_t w = pos >> 5, sh = pos & 31u;
@@ -339,24 +347,24 @@ __device__ inline void br_init(BitReader &r, const uint32_t *wp, uint32_t cw, ui
   r.buf = (((uint64_t)w0 << 32) | w1) << sh;
   r.nb = 64u - sh;
   r.wi = w + 2;
-  r.pend = r.wi < cw ? wp[r.wi] : 0u;
+  r.pend = wp[min(r.wi, cw - 1u)];
 }
 __device__ inline uint32_t br_peek(const BitReader &r) { return (uint32_t)(r.buf >> 32); }
 __device__ inline void br_skip(BitReader &r, uint32_t len) {
   r.buf <<= len;
   r.nb -= len;
   if (r.nb < 32u) {
-    r.buf |= (uint64_t)r.pend << (32u - r.nb);
+    r.buf |= (uint64_t)(r.wi < r.cw ? r.pend : 0u) << (32u - r.nb);
     r.nb += 32u;
     r.wi++;
-    r.pend = r.wi < r.cw ? r.wp[r.wi] : 0u;
+    r.pend = r.wp[min(r.wi, r.cw - 1u)];
   }
 }
 
-// length of the codeword at the front of a 32-bit window (1 for a pattern
-// that is no codeword: speculative decoding keeps going)
-__device__ inline uint32_t decode_len(const DecTab &T, uint32_t win) {
-  const uint32_t e = T.lut[win >> (32 - kLutBits)];
+// length of the codeword at the front of a 32-bit window, given its
+// first-level entry e (1 for a pattern that is no codeword: speculative
+// decoding keeps going)
+__device__ inline uint32_t decode_len(const DecTab &T, uint32_t e, uint32_t win) {
   uint32_t len = (e >> 16) & 31u;
   if (e & kLutLong) {
     while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
@@ -372,7 +380,8 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
   while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
   if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
   const uint32_t code = win >> (32 - len);
-  return (uint32_t)T.syms[T.base[len] + (code - T.first[len])] | (len << 16);
+  const uint32_t idx = T.base[len] + (code - T.first[len]);
+  return (uint32_t)(T.syms_lds ? T.lsyms[idx] : T.gsyms[idx]) | (len << 16);
 }
 
 // One wave decodes block b of a stream and stores its floats.
@@ -386,10 +395,10 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
 // the reconstructed floats are stored straight from registers, coalesced.
 __device__ __forceinline__ uint32_t qaddr(uint32_t e) { return e + 2u * (e >> 6); }
 
-__device__ __forceinline__ void decode_block(const DField &df, const DState *st, const DecTab &T, uint32_t b,
+__device__ __forceinline__ void decode_block(const DField &df, gptr<const DState> st, const DecTab &T, uint32_t b,
                                              uint16_t *q16, int *bad_flag) {
   const uint32_t l = lane_id();
-  const uint8_t *in = df.in;
+  const gptr<const uint8_t> in = G(df.in);
   const uint32_t S = st->S;
   const uint32_t len = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
   const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
@@ -397,9 +406,9 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
   const uint32_t k = st->policy >= 2 ? in[st->off_pred + b] : st->policy;
   const int32_t p0 = (int32_t)rd32(in, st->off_pfirst + 4ull * b);
   const uint32_t R = n_ranges(cw), swd = skip_width(T.maxlen), skw = skip_words(cw, T.maxlen);
-  const uint32_t *sk = reinterpret_cast<const uint32_t *>(in + st->off_payload) + df.boff[b];
-  const uint32_t *wp = sk + skw;
-  const uint32_t *esc = wp + cw;
+  const gptr<const uint32_t> sk = reinterpret_cast<gptr<const uint32_t>>(in + st->off_payload) + G(df.boff)[b];
+  const gptr<const uint32_t> wp = sk + skw;
+  const gptr<const uint32_t> esc = wp + cw;
   uint32_t invalid = 0;
 
   // bring the block's words into cache with a coalesced sweep, so that the
@@ -431,16 +440,16 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
       const uint32_t win = br_peek(br);
       const uint32_t ent = T.lut[win >> (32 - kLutBits)];
       const uint32_t mc = (ent >> 24) & 15u, ml = ent >> 28;
+      uint32_t ln, c = 1;
       if (mc >= 2u && pos + ml <= e) {  // several whole codes, all starting before e
-        pos += ml;
-        br_skip(br, ml);
-        cnt += mc;
-        continue;
+        ln = ml;
+        c = mc;
+      } else {
+        ln = decode_len(T, ent, win);
       }
-      const uint32_t ln = decode_len(T, win);
       pos += ln;
       br_skip(br, ln);
-      cnt++;
+      cnt += c;
     }
   }
   // the codeword that ends a range must be where the next range's entry points
@@ -460,22 +469,23 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
           const uint32_t win = br_peek(br);
           const uint32_t m = T.lut2[win >> (32 - kLutBits)];
           const uint32_t n2 = (m >> 24) & 3u, l2 = (m >> 26) & 15u;
+          uint32_t ln, adv;
           if (n2 >= 2u && p + l2 <= e && i + n2 <= len) {  // two or three small symbols at once
             q16[qaddr(i)] = (uint16_t)(kRadius + (int32_t)(int8_t)(m & 255u));
             q16[qaddr(i + 1)] = (uint16_t)(kRadius + (int32_t)(int8_t)((m >> 8) & 255u));
             if (n2 == 3u) q16[qaddr(i + 2)] = (uint16_t)(kRadius + (int32_t)(int8_t)((m >> 16) & 255u));
-            p += l2;
-            br_skip(br, l2);
-            i += n2;
-            continue;
+            ln = l2;
+            adv = n2;
+          } else {
+            const uint32_t r = decode_sym(T, win);
+            ln = (r >> 16) & 31u;
+            if (r & kLutInvalid) invalid = 1;
+            q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
+            adv = 1;
           }
-          const uint32_t r = decode_sym(T, win);
-          const uint32_t ln = (r >> 16) & 31u;
-          if (r & kLutInvalid) invalid = 1;
-          q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
           p += ln;
           br_skip(br, ln);
-          i++;
+          i += adv;
         }
       } else {
         while (p < e && i < len) {
@@ -495,7 +505,7 @@ __device__ __forceinline__ void decode_block(const DField &df, const DState *st,
   const uint64_t lt = l ? (~0ull >> (64 - l)) : 0ull;
   uint32_t c0 = 0, c1 = 0, c2 = 0, ebase = 0;
   const double step = st->step, mn = (double)st->mn;
-  float *out = df.out + (uint64_t)b * S;
+  const gptr<float> out = G(df.out) + (uint64_t)b * S;
   if (l == 0 && len && q16[0] != (uint16_t)kRadius) invalid = 1;
   for (uint32_t row = 0; row < len; row += kWave) {
     const uint32_t el = row + l;
@@ -568,12 +578,12 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     }
     const int pair = lo, f = pair / 3, k = pair % 3;
     const DField &df = D[f];
-    const DState *st = df.st;
+    const gptr<const DState> st = G(static_cast<const DState *>(df.st));
     if (pair != cur) {
       __syncthreads();
-      const uint32_t *gl = df.lut + (uint64_t)k * (2u << kLutBits);
+      const gptr<const uint32_t> gl = G(df.lut) + (uint64_t)k * (2u << kLutBits);
       for (uint32_t i = t; i < lut_words; i += blockDim.x) s_lut[i] = gl[i];
-      const uint32_t *gs = df.slow + (uint64_t)k * kSlowWords;
+      const gptr<const uint32_t> gs = G(df.slow) + (uint64_t)k * kSlowWords;
       for (uint32_t i = t; i < 32u; i += blockDim.x) {
         s_first[i] = gs[i];
         s_base[i] = gs[32 + i];
@@ -582,7 +592,7 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
       const uint32_t ns = st->nsym[k];
       syms_lds = ns <= symcap;
       if (syms_lds) {
-        const uint16_t *gsy = df.syms + (uint64_t)k * kNSyms;
+        const gptr<const uint16_t> gsy = G(df.syms) + (uint64_t)k * kNSyms;
         for (uint32_t i = t; i < ns; i += blockDim.x) s_syms[i] = gsy[i];
       }
       __syncthreads();
@@ -595,14 +605,16 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     T2.first = s_first;
     T2.base = s_base;
     T2.limit = s_limit;
-    T2.syms = syms_lds ? s_syms : df.syms + (uint64_t)k * kNSyms;
+    T2.lsyms = s_syms;
+    T2.gsyms = G(df.syms) + (uint64_t)k * kNSyms;
+    T2.syms_lds = syms_lds;
     T2.maxlen = st->maxlen[k];
     const uint32_t idx = (task - tbase[pair]) * dw + w;
     if (idx < st->grp_count[k]) {
-      const uint32_t b = df.order[st->grp_start[k] + idx];
+      const uint32_t b = G(df.order)[st->grp_start[k] + idx];
       int bad = 0;
       decode_block(df, st, T2, b, reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * (smax + smax / 32u)), &bad);
-      if (bad && lane_id() == 0) atomicCAS((int *)&df.st->status, 0, SZNB_ECORRUPT);
+      if (bad && lane_id() == 0) atomicCAS(&df.st->status, 0, SZNB_ECORRUPT);
     }
   }
 }

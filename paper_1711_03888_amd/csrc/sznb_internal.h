@@ -44,6 +44,20 @@ constexpr uint32_t kMagic = 0x424E5A53u;  // "SZNB"
 
 __host__ __device__ inline uint64_t align8(uint64_t x) { return (x + 7) & ~uint64_t(7); }
 
+// Global-memory view of a pointer.  Kernels reach their buffers through
+// pointers held in descriptor tables; such a pointer could as well address
+// LDS, so the compiler accesses it with flat instructions, and a flat load
+// in flight counts on the LDS wait counter too: every wait for an LDS read
+// would also wait for it.  Through the global address space the loads and
+// stores are global_* and LDS waits stay short.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+template <class T>
+__device__ __forceinline__ gptr<T> G(T *p) {
+  return (gptr<T>)p;
+}
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Section offsets that depend only on the block count and the policy.
 struct Sections {
   uint64_t pred, pfirst, cwords, nesc, books;
@@ -104,9 +118,12 @@ struct alignas(16) CField {
 };
 constexpr int kBookWords = 32 + kNSyms / 2;
 
+constexpr int kHuffSlots = 64;  // Huffman workgroups (and scratch slots), at most
 struct alignas(64) GCtl {
   uint32_t ticket;        // block tickets of the pack kernel
   uint32_t pad[15];
+  uint32_t hdone[kHuffSlots];  // Huffman variants finished, per (field, predictor) pair
+  uint32_t hres[kHuffSlots];   // per Huffman workgroup: its code lengths fit
 };
 
 // Skip table of a block: its code words are cut into R word-aligned ranges
@@ -302,10 +319,10 @@ __device__ inline int find_field(const uint64_t *fblock0, int nf, uint64_t g) {
 // Coherent (agent-scope) relaxed accesses.  Acquire/release would add cache
 // write-back and invalidation to every access; the look-back words carry all
 // the information their readers need, so none is required.
-__device__ inline uint64_t ld_relaxed_u64(const uint64_t *p) {
+__device__ inline uint64_t ld_relaxed_u64(gptr<const uint64_t> p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_relaxed_u64(uint64_t *p, uint64_t v) {
+__device__ inline void st_relaxed_u64(gptr<uint64_t> p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 

@@ -209,3 +209,56 @@ def test_histogram_counter_wraps():
     got, y = _gpu_roundtrip(x, 1e-3, sznb.PRED_LV | sznb.EB_REL)
     assert got == ref
     assert np.abs(y.astype(np.float64) - x).max() <= oracle.header(ref)["eb_abs"]
+
+
+def _unlimited_huffman_depth(w):
+    """Depth of the deepest leaf of a Huffman tree without a length limit
+    (heap merge of the two lightest nodes)."""
+    import heapq
+    h = [(int(v), i, 0) for i, v in enumerate(w)]
+    heapq.heapify(h)
+    nxt = len(h)
+    while len(h) > 1:
+        a, b = heapq.heappop(h), heapq.heappop(h)
+        heapq.heappush(h, (a[0] + b[0], nxt, max(a[2], b[2]) + 1))
+        nxt += 1
+    return h[0][2]
+
+
+_DEEP = {}
+
+
+def _deep_field():
+    # x coordinates of a 2^24-particle snapshot: at eb_rel 1e-4 the LV code
+    # is deeper than 24 bits until the weights are halved once
+    if "x" not in _DEEP:
+        n = 1 << 24
+        snap = datagen.cosmology(n, seed=3, n_halos=max(1, int(20000 * n / float(1 << 26))))
+        x = snap["xx"]
+        q = oracle.lattice(x, 1e-4)
+        r = oracle.residuals(q, 4096, 0)
+        h = np.bincount(np.where(np.abs(r) < 32768, r + 32768, 0), minlength=65536)
+        w = h[h > 0].astype(np.int64)
+        depths = [_unlimited_huffman_depth(w)]
+        while depths[-1] > 24:
+            w = (w + 1) // 2
+            depths.append(_unlimited_huffman_depth(w))
+        _DEEP["x"], _DEEP["depths"] = x, depths
+        _DEEP["ref"] = oracle.compress(x, 1e-4, sznb.PRED_LV | sznb.EB_REL)
+    return _DEEP["x"], _DEEP["depths"], _DEEP["ref"]
+
+
+@pytest.mark.parametrize("nextra", [0, 7, 10])
+def test_huffman_length_limit_variants(nextra):
+    # one field: four workgroups per (field, predictor) pair, starting from
+    # 0..3 halvings; eight fields: two; eleven fields: one per pair, which
+    # halves in turn.  The code must be the one the sequential rule picks.
+    x, depths, ref = _deep_field()
+    print("length limit, %d extra fields, depths %s" % (nextra, depths), flush=True)
+    assert depths[0] > 24 and len(depths) == 2
+    mode = sznb.PRED_LV | sznb.EB_REL
+    fields = [x] + [datagen.random_walk(5000 + 701 * i, seed=60 + i) for i in range(nextra)]
+    outs = sznb.compress_batch([torch.from_numpy(np.ascontiguousarray(f)).cuda() for f in fields], 1e-4, mode)
+    assert bytes(outs[0].cpu().numpy()) == ref
+    for f, o in zip(fields[1:], outs[1:]):
+        assert bytes(o.cpu().numpy()) == oracle.compress(f, 1e-4, mode)
