@@ -1205,10 +1205,11 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
-    int32_t d[E], pv[3], p0;
-    load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
+    // the block's predictor is read along with its values
     const gptr<uint8_t> out = G(c.out);
     const int pred = c.policy >= 2 ? (int)out[c.sec.pred + b] : (int)c.policy;
+    int32_t d[E], pv[3], p0;
+    load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
     const int slot = c.policy >= 2 ? pred : 0;
     const gptr<const uint32_t> enc = G(c.enc) + (uint64_t)slot * kNSyms;
 
@@ -1278,7 +1279,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     // skip table entries of the range starts inside this thread's bits
     if (bits && R > 1) {
       const uint32_t w0 = (bit0 + 31) >> 5;
-      uint32_t lr = (uint32_t)(((uint64_t)w0 * R + cwn - 1) / cwn);
+      uint32_t lr = (w0 * R + cwn - 1) / cwn;
       if (lr < 1) lr = 1;
       for (; lr < R; lr++) {
         const uint32_t st0 = range_start(lr, cwn, R);

@@ -144,7 +144,7 @@ __host__ __device__ inline uint32_t skip_words(uint32_t cw, uint32_t maxlen) {
   return ((n_ranges(cw) - 1) * skip_width(maxlen) + 31) / 32;
 }
 __host__ __device__ inline uint32_t range_start(uint32_t l, uint32_t cw, uint32_t R) {
-  return 32u * (uint32_t)(((uint64_t)l * cw) / R);
+  return 32u * ((l * cw) / R);  // l <= 64 and cw <= 2^14 * 24 / 32: no overflow
 }
 
 // predictor that histogram slot s of a field codes
