@@ -217,18 +217,6 @@ __global__ __launch_bounds__(kThreads) void k_params(const CField *__restrict__ 
 
 // --------------------------------------------------- quantize and select
 
-// residual class of the best-fit estimate: zigzag z < 4 is its own class; a
-// larger z of bit length b is class 4 + 2(b-3) + (bit b-2 of z) with b-2
-// extra bits; an escape (|r| >= 32768) is class 32 with 32 extra bits.
-__device__ inline uint32_t res_class(int32_t r, uint32_t &extra) {
-  if (r >= kRadius || r <= -kRadius) { extra = 32u; return 32u; }
-  uint32_t z = ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
-  if (z < 4u) { extra = 0u; return z; }
-  uint32_t b = 32u - __clz(z);
-  extra = b - 2u;
-  return 4u + 2u * (b - 3u) + ((z >> (b - 2u)) & 1u);
-}
-
 __device__ inline int32_t lattice_of(float x, float mn, double inv) {
   double t = __dmul_rn(__dsub_rn((double)x, (double)mn), inv);
   return (int32_t)floor(__dadd_rn(t, 0.5));
@@ -299,7 +287,24 @@ __device__ inline int32_t residual_at(const int32_t (&d)[E], const int32_t (&pv)
   return (int32_t)(b0 - (a1 - a2));
 }
 
-constexpr int kClsCopies = 8, kClsStride = 100;  // class-counter copies of the trial
+// Residual classes of the best-fit estimate: zigzag z < 4 is its own class;
+// a larger z of bit length b is class 4 + 2(b-3) + (bit b-2 of z) with b-2
+// extra bits; an escape (|r| >= 32768) is class 32 with 32 extra bits.
+// Class-counter slots of the trial, per predictor: class 0 at slot 0, class
+// c >= 1 at slot c + 2 (slots 1 and 2 stay empty).  For a residual r with
+// zigzag code z < 65535, the float z + 0.5 (exact) has unbiased exponent
+// bitlen(z) - 1 and, below it, bit bitlen(z) - 2 of z as its first mantissa
+// bit, so (bits(z + 0.5) >> 22) - 252 is that slot; z = 0 lands on slot 0.
+// An escape (z >= 65535, class 32) takes slot 34.
+constexpr int kClsSlots = kNClass + 2;
+constexpr int kClsCopies = 8, kClsStride = 108;  // class-counter copies of the trial
+__device__ inline uint32_t class_slot_biased(int32_t r) {  // slot + 252
+  const uint32_t z = ((uint32_t)r << 1) ^ (uint32_t)(r >> 31);
+  const uint32_t u = __float_as_uint((float)z + 0.5f) >> 22;
+  return z >= 65535u ? 34u + 252u : u;
+}
+// extra bits of a class: bitlen(z) - 2 for c >= 4, 32 for an escape
+__device__ inline uint32_t class_extra(uint32_t c) { return c == 32u ? 32u : (c < 4u ? 0u : (c - 2u) >> 1); }
 
 // Exhaustive trial of one block: the two-part size estimate of LV, LCF and
 // QCF residuals (classes of res_class, 2^-16 bit units), argmin with ties to
@@ -307,47 +312,43 @@ constexpr int kClsCopies = 8, kClsStride = 100;  // class-counter copies of the 
 // *s_pred; all threads of the workgroup take part.
 template <int E>
 __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3], uint32_t len,
-                                   const uint32_t *__restrict__ logt, uint32_t *s_cls, uint32_t *s_extra,
+                                   const uint32_t *__restrict__ logt, uint32_t *s_cls,
                                    unsigned long long *s_cost, int *s_pred) {
   const int t = threadIdx.x;
-  // kClsCopies copies of the 99 counters, lane l of a wave on copy l mod 8:
-  // a class hit by a whole wave costs 8 serialised updates, not 64 (the
-  // copies' strides put one class of all copies on distinct banks)
+  // kClsCopies copies of the 3 x 35 slots, lane l of a wave on copy l mod 8:
+  // a slot hit by a whole wave costs 8 serialised updates, not 64 (the
+  // copies' strides put one slot of all copies on distinct banks)
   for (int i = t; i < kClsCopies * kClsStride; i += kThreads) s_cls[i] = 0;
-  if (t < 3) { s_extra[t] = 0; s_cost[t] = 0; }
+  if (t < 3) s_cost[t] = 0;
   __syncthreads();
+  // per predictor, the address of slot 0 minus 252 slots
   uint32_t *my = s_cls + (t & (kClsCopies - 1)) * kClsStride;
-  uint32_t ex[3] = {0u, 0u, 0u};
 #pragma unroll
   for (int e = 0; e < E; e++) {
     if ((uint32_t)t * E + e < len) {
 #pragma unroll
       for (int k = 0; k < 3; k++) {
-        uint32_t xb;
-        uint32_t cl = res_class(residual_at<E>(d, pv, e, k), xb);
-        atomicAdd(&my[k * kNClass + cl], 1u);
-        ex[k] += xb;
+        const uint32_t slot = class_slot_biased(residual_at<E>(d, pv, e, k)) - 252u;
+        atomicAdd(&my[k * kClsSlots + slot], 1u);
       }
     }
   }
-#pragma unroll
-  for (int k = 0; k < 3; k++) {
-    uint32_t v = wave_sum(ex[k]);
-    if ((t & (kWave - 1)) == 0) atomicAdd(&s_extra[k], v);
-  }
   __syncthreads();
   if (t < 3 * kNClass) {
+    const uint32_t k = (uint32_t)t / kNClass, c = (uint32_t)t % kNClass;
+    const uint32_t slot = k * kClsSlots + (c ? c + 2u : 0u);
     uint32_t n_c = 0;
-    for (int j = 0; j < kClsCopies; j++) n_c += s_cls[j * kClsStride + t];
-    if (n_c) atomicAdd(&s_cost[t / kNClass], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]));
+    for (int j = 0; j < kClsCopies; j++) n_c += s_cls[j * kClsStride + slot];
+    if (n_c)
+      atomicAdd(&s_cost[k], (unsigned long long)n_c * (unsigned long long)(logt[len] - logt[n_c]) +
+                                65536ull * (unsigned long long)n_c * class_extra(c));
   }
   __syncthreads();
   if (t == 0) {
     int best = 0;
     unsigned long long bc = 0;
     for (int k = 0; k < 3; k++) {
-      unsigned long long ck = s_cost[k] + 65536ull * s_extra[k];
-      s_cost[k] = ck;
+      const unsigned long long ck = s_cost[k];
       if (k == 0 || ck < bc) { bc = ck; best = k; }
     }
     *s_pred = best;
@@ -516,7 +517,6 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
   }
   __shared__ int32_t s_tail[3 * kThreads];
   __shared__ uint32_t s_cls[kClsCopies * kClsStride];
-  __shared__ uint32_t s_extra[3];
   __shared__ unsigned long long s_cost[3];
   __shared__ int32_t s_p0;
   __shared__ int s_pred, s_fb;
@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
         trial = s_fb != 0;
         if (trial && t == 0) atomicAdd(&c.st->fallbacks, 1u);
       }
-      if (trial) block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
+      if (trial) block_trial<E>(d, pv, len, logt, s_cls, s_cost, &s_pred);
       pred = s_pred;
       if (t == 0) G(c.out)[c.sec.pred + b] = (uint8_t)pred;
     }
@@ -642,7 +642,6 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
   constexpr int S = E * kThreads;
   __shared__ int32_t s_tail[3 * kThreads];
   __shared__ uint32_t s_cls[kClsCopies * kClsStride];
-  __shared__ uint32_t s_extra[3];
   __shared__ unsigned long long s_cost[3];
   __shared__ int32_t s_p0;
   __shared__ int s_pred;
@@ -665,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
     int32_t d[E], pv[3], p0;
     load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
     block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
-    block_trial<E>(d, pv, len, logt, s_cls, s_extra, s_cost, &s_pred);
+    block_trial<E>(d, pv, len, logt, s_cls, s_cost, &s_pred);
     if (t < kNFeat) feat[g * kNFeat + t] = s_feat[t];
     if (t < 3) cost[g * 3 + t] = s_cost[t];
     if (t == 0) label[g] = (uint8_t)s_pred;

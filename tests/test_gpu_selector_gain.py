@@ -2,7 +2,10 @@
 
 * nbody selector (trained on random-walk and cosmology blocks, where the
   exhaustive trial picks LV everywhere): same ratio as the exhaustive trial
-  within 1 %, and a faster quantization kernel, since the trial is skipped.
+  within 1 %.  Its quantization kernel time is reported beside the trial's:
+  the trial costs about nine instructions per value and predictor, less than
+  the selector's features and network, so skipping it no longer pays; the
+  bound below only guards against a gross slowdown.
 * md selector (trained on FCC coordinate blocks, where LCF wins about a
   quarter of the blocks): ratio within 1 % of the exhaustive trial and above
   the fixed LV predictor, the method without a selector.
@@ -58,7 +61,7 @@ def test_nbody_selector_gain():
     print("ratio exhaustive %.4f learned %.4f; k_quant %.3f ms -> %.3f ms; fallbacks %d"
           % (rb, rl, q_b, q_l, fb), flush=True)
     assert rl >= 0.99 * rb
-    assert q_l < 1.1 * q_b  # no slower: the trial is not what bounds the kernel
+    assert q_l < 2.0 * q_b
     # the first field decodes to the oracle's floats with the same choices
     ref = oracle.compress(fields[0], eb, sznb.PRED_LEARNED | sznb.EB_REL, selector=(params, tau))
     assert bytes(sl[0].cpu().numpy()) == ref
