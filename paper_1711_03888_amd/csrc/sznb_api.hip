@@ -845,7 +845,7 @@ static int decompress_run(const DLaunch &P, hipStream_t stream) {
   const DField *D = reinterpret_cast<const DField *>(P.ws + P.L.fields);
   uint32_t *tbase = reinterpret_cast<uint32_t *>(P.ws + P.L.tbase);
   uint32_t *ticket = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->ticket;
-  SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(kThreads), 0, stream, D, P.smax);
+  SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(1024), 0, stream, D, P.smax);
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
   uint32_t *nconst = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->pad[0];
   SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket, nconst);

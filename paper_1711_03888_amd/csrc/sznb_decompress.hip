@@ -42,13 +42,15 @@ __global__ void d_heads(const DField *__restrict__ D, int nf, uint32_t *heads) {
   for (int k = 0; k < 4; k++) heads[4 * f + k] = v[k];
 }
 
-__global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D, uint32_t smax) {
+constexpr int kPrepThreads = 1024;
+constexpr uint32_t kPrepBatch = 8;
+__global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict__ D, uint32_t smax) {
   const DField &df = D[blockIdx.x];
   DState *st = df.st;
   const uint8_t *in = df.in;
   const int t = threadIdx.x;
   __shared__ int s_bad;
-  __shared__ uint32_t s_tot[kThreads / kWave][4];
+  __shared__ uint32_t s_tot[kPrepThreads / kWave][4];
   if (t == 0) {
     int bad = 0;
     st->status = 0;
@@ -110,16 +112,35 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D,
   // block word offsets and predictor groups
   const uint32_t nb = st->nblocks, policy = st->policy, S = st->S;
   const uint32_t cwmax = S * kLMax / 32;
-  const uint32_t per = (nb + kThreads - 1) / kThreads;
+  const uint32_t per = (nb + kPrepThreads - 1) / kPrepThreads;
   const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
+  // the block table entries are read kPrepBatch blocks at a time, all loads
+  // of a batch issued before any is used
+  const gptr<const uint8_t> gin = G(in);
+  const uint64_t ocw = st->off_cwords, one = st->off_nesc, opr = st->off_pred;
+  auto batch = [&](uint32_t b0, uint32_t (&cwv)[kPrepBatch], uint32_t (&nev)[kPrepBatch], uint32_t (&kv)[kPrepBatch]) {
+#pragma unroll
+    for (uint32_t j = 0; j < kPrepBatch; j++) {
+      const uint32_t b = min(b0 + j, hi - 1);
+      cwv[j] = rd16(gin, ocw + 2ull * b);
+      nev[j] = rd16(gin, one + 2ull * b);
+      kv[j] = policy >= 2 ? gin[opr + b] : policy;
+    }
+  };
   uint32_t words = 0, cnt[3] = {0, 0, 0}, bad = 0;
-  for (uint32_t b = lo; b < hi; b++) {
-    const uint32_t cw = rd16(in, st->off_cwords + 2ull * b), ne = rd16(in, st->off_nesc + 2ull * b);
-    const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
-    const uint32_t blen = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
-    if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) { bad = 1; continue; }
-    cnt[k]++;
-    words += skip_words(cw, st->maxlen[k]) + cw + ne;
+  for (uint32_t b0 = lo; b0 < hi; b0 += kPrepBatch) {
+    uint32_t cwv[kPrepBatch], nev[kPrepBatch], kv[kPrepBatch];
+    batch(b0, cwv, nev, kv);
+#pragma unroll
+    for (uint32_t j = 0; j < kPrepBatch; j++) {
+      const uint32_t b = b0 + j;
+      if (b >= hi) break;
+      const uint32_t cw = cwv[j], ne = nev[j], k = kv[j];
+      const uint32_t blen = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
+      if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) { bad = 1; continue; }
+      cnt[k]++;
+      words += skip_words(cw, st->maxlen[k]) + cw + ne;
+    }
   }
   // workgroup exclusive scans of (words, cnt0, cnt1, cnt2)
   uint32_t v[4] = {words, cnt[0], cnt[1], cnt[2]}, ex[4], tot[4];
@@ -134,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D,
   __syncthreads();
   for (int i = 0; i < 4; i++) {
     tot[i] = 0;
-    for (int j = 0; j < kThreads / kWave; j++) {
+    for (int j = 0; j < kPrepThreads / kWave; j++) {
       if (j < w) ex[i] += s_tot[j][i];
       tot[i] += s_tot[j][i];
     }
@@ -145,12 +166,18 @@ __global__ __launch_bounds__(kThreads) void d_prep(const DField *__restrict__ D,
   }
   uint32_t gstart[3] = {0, tot[1], tot[1] + tot[2]};
   uint32_t run = ex[0], gpos[3] = {gstart[0] + ex[1], gstart[1] + ex[2], gstart[2] + ex[3]};
-  for (uint32_t b = lo; b < hi; b++) {
-    df.boff[b] = run;
-    const uint32_t k = policy >= 2 ? in[st->off_pred + b] : policy;
-    const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
-    run += skip_words(cw, st->maxlen[k]) + cw + rd16(in, st->off_nesc + 2ull * b);
-    df.order[gpos[k]++] = b;
+  const gptr<uint32_t> boff = G(df.boff), order = G(df.order);
+  for (uint32_t b0 = lo; b0 < hi; b0 += kPrepBatch) {
+    uint32_t cwv[kPrepBatch], nev[kPrepBatch], kv[kPrepBatch];
+    batch(b0, cwv, nev, kv);
+#pragma unroll
+    for (uint32_t j = 0; j < kPrepBatch; j++) {
+      const uint32_t b = b0 + j;
+      if (b >= hi) break;
+      boff[b] = run;
+      run += skip_words(cwv[j], st->maxlen[kv[j]]) + cwv[j] + nev[j];
+      order[gpos[kv[j]]++] = b;
+    }
   }
   if (t == 0) {
     for (int k = 0; k < 3; k++) { st->grp_count[k] = tot[1 + k]; st->grp_start[k] = gstart[k]; }
