@@ -250,17 +250,20 @@ __device__ inline void block_d_from_raw(const float (&v)[E], float mn, double in
   int32_t p[E];
 #pragma unroll
   for (int e = 0; e < E; e++) p[e] = lattice_of(v[e], mn, inv);
+  // the anchor and every thread's last three lattice values, one barrier
   if (t == 0) *s_p0 = p[0];
+  s_tail[3 * t + 0] = p[E - 1];
+  s_tail[3 * t + 1] = p[E - 2];
+  s_tail[3 * t + 2] = p[E - 3];
   __syncthreads();
   const int32_t p0 = *s_p0;
 #pragma unroll
   for (int e = 0; e < E; e++) d[e] = (int32_t)((uint32_t)p[e] - (uint32_t)p0);
-  s_tail[3 * t + 0] = d[E - 1];
-  s_tail[3 * t + 1] = d[E - 2];
-  s_tail[3 * t + 2] = d[E - 3];
-  __syncthreads();
   if (t == 0) { pv[0] = pv[1] = pv[2] = 0; }
-  else { pv[0] = s_tail[3 * (t - 1)]; pv[1] = s_tail[3 * (t - 1) + 1]; pv[2] = s_tail[3 * (t - 1) + 2]; }
+  else {
+#pragma unroll
+    for (int i = 0; i < 3; i++) pv[i] = (int32_t)((uint32_t)s_tail[3 * (t - 1) + i] - (uint32_t)p0);
+  }
   p0_out = p0;
 }
 
