@@ -26,6 +26,7 @@ namespace sznb {
 constexpr uint32_t kSeg = 16384;
 constexpr uint32_t kSub = 256;   // keys per decoder entry point (kSeg / kSub = 64 lanes)
 constexpr uint32_t kEscQ = 32;   // quotients from 32 on are escaped
+constexpr uint32_t kCpcLdsWords = 16384;  // decoder: a segment's code words staged in LDS (64 KiB)
 constexpr int kMT = 1024;
 constexpr int kMW = kMT / kWave;
 
@@ -380,7 +381,8 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   }
   const uint32_t *sb = reinterpret_cast<const uint32_t *>(cs + kCpHdr);
   uint64_t woff = 0;
-  for (uint32_t s = 0; s < seg; s++) woff += (sb[s] + 31) / 32;
+  for (uint32_t s = lane; s < seg; s += kWave) woff += (sb[s] + 31) / 32;
+  woff = wave_sum(woff);
   const uint64_t nbits = sb[seg];
   const uint64_t avail = (cs_len - tab) / 4;
   bool bad = woff + (nbits + 31) / 32 > avail;
@@ -390,16 +392,46 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   const uint32_t m = (uint32_t)min((uint64_t)kSeg, n - base);
   const uint32_t k0 = lane * kSub, k1 = min(m, k0 + kSub);  // this lane's keys
   const bool active = k0 < m;
-  uint64_t pos = 0;
-  auto take = [&](uint32_t nb) -> uint64_t {  // nb <= 32, never past nbits
-    if (!nb) return 0;
-    if (pos + nb > nbits) { bad = true; pos = nbits; return 0; }
-    const uint64_t wi = pos >> 5;
-    const uint32_t sh = pos & 31u;
-    const uint64_t w1 = (sh + nb > 32u) ? wp[wi + 1] : 0u;
-    const uint64_t v = ((uint64_t)wp[wi] << 32) | w1;
+  // Bit reader of this lane: a 64-bit window holding the bits from pos on
+  // (more than 32 of them after every refill), words past the segment read
+  // as zero; a read that would pass nbits marks the segment corrupt.
+  const gptr<const uint32_t> gw = G(wp);
+  const uint64_t nw = (nbits + 31) / 32;
+  // the segment's words are staged in LDS when they fit (one coalesced
+  // sweep; both passes then refill from LDS)
+  __shared__ uint32_t s_seg[kCpcLdsWords];
+  const bool in_lds = !bad && nw <= kCpcLdsWords;
+  if (in_lds)
+    for (uint32_t i = lane; i < nw; i += kWave) s_seg[i] = gw[i];
+  __syncthreads();
+  auto word = [&](uint64_t i) -> uint32_t { return i >= nw ? 0u : (in_lds ? s_seg[i] : gw[i]); };
+  uint64_t pos = 0, buf = 0, wi = 0;
+  uint32_t nv = 0;
+  auto seek = [&](uint64_t p) {
+    pos = p;
+    wi = p >> 5;
+    const uint32_t sh = (uint32_t)(p & 31u);
+    const uint64_t w0 = word(wi), w1 = word(wi + 1);
+    buf = ((w0 << 32) | w1) << sh;
+    nv = 64u - sh;
+    wi += 2;
+  };
+  auto skip = [&](uint32_t nb) {  // nb <= 32
+    buf = nb ? buf << nb : buf;
+    nv -= nb;
     pos += nb;
-    return (v << sh) >> (64 - nb);
+    if (nv <= 32u) {
+      buf |= (uint64_t)word(wi) << (32u - nv);
+      nv += 32u;
+      wi++;
+    }
+  };
+  auto take = [&](uint32_t nb) -> uint64_t {  // nb <= 32
+    if (!nb) return 0;
+    if (pos + nb > nbits) { bad = true; return 0; }
+    const uint64_t v = buf >> (64u - nb);
+    skip(nb);
+    return v;
   };
   auto take_wide = [&](uint32_t nb) -> uint64_t {
     if (nb > 32u) { const uint64_t hi = take(nb - 32u); return (hi << 32) | take(32u); }
@@ -408,7 +440,7 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   // the Rice parameter follows the first key
   uint32_t r = 0;
   if (!bad) {
-    pos = kb;
+    seek(kb);
     r = (uint32_t)take(6);
     if (r > kb) bad = true;
   }
@@ -417,15 +449,19 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
   auto next = [&](uint32_t i) -> uint64_t {  // delta of key i (the raw key for i = 0)
     if (i == 0) { const uint64_t k = take_wide(kb); (void)take(6); return k; }
-    uint32_t q = 0;
-    while (q < kEscQ && !bad && take(1)) q++;
+    // unary quotient: the ones before the first zero, at most kEscQ (= 32)
+    const uint32_t ones = ~(uint32_t)(buf >> 32);
+    const uint32_t q = ones ? (uint32_t)__clz(ones) : kEscQ;
+    const uint32_t ub = q < kEscQ ? q + 1u : kEscQ;
+    if (pos + ub > nbits) { bad = true; return 0; }
+    skip(ub);
     if (q == kEscQ) return take_wide(kb);
     return ((uint64_t)q << r) | take_wide(r);
   };
   // pass 1: sum of this lane's deltas
   uint64_t sum = 0;
   if (active && !bad) {
-    pos = start;
+    seek(start);
     for (uint32_t i = k0; i < k1 && !bad; i++) sum += next(i);
     if (pos != stop) bad = true;
   }
@@ -443,7 +479,7 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   // pass 2: keys and coordinates
   if (!active) return;
   uint64_t k = inc - sum;
-  pos = start;
+  seek(start);
   for (uint32_t i = k0; i < k1; i++) {
     k += next(i);
     const uint32_t px = compact3(k >> 2), py = compact3(k >> 1), pz = compact3(k);
