@@ -116,11 +116,23 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
   uint32_t *ia = i0 + base, *ib = i1 + base;
   const uint32_t segw = (m + kMW - 1) / kMW;
   const uint32_t beg = min(m, segw * w), end = min(m, beg + segw);
+  // the wave's keys and indices of a pass are read once, in one round trip
+  constexpr int kPL = kSeg / kMT;  // chunks of 64 per wave
   for (uint32_t ps = 0; ps < passes; ps++) {
     const uint32_t sh = shift0 + 8 * ps;
+    uint64_t kv[kPL];
+    uint32_t iv[kPL];
+#pragma unroll
+    for (int c = 0; c < kPL; c++) {
+      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
+      kv[c] = i < end ? ka[i] : 0ull;
+      iv[c] = i < end ? ia[i] : 0u;
+    }
     for (uint32_t i = t; i < 256u * kMW; i += kMT) s_cnt[i] = 0;
     __syncthreads();
-    for (uint32_t i = beg + lane_id(); i < end; i += kWave) atomicAdd(&s_cnt[((ka[i] >> sh) & 255u) * kMW + w], 1u);
+#pragma unroll
+    for (int c = 0; c < kPL; c++)
+      if (beg + (uint32_t)c * kWave + lane_id() < end) atomicAdd(&s_cnt[((kv[c] >> sh) & 255u) * kMW + w], 1u);
     __syncthreads();
     // exclusive scan over (digit, wave), digit-major
     uint32_t loc = 0;
@@ -132,11 +144,11 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
     for (int j = 0; j < w; j++) run += s_tot[j];
     for (int j = 0; j < 4; j++) { const uint32_t v = s_cnt[4 * t + j]; s_cnt[4 * t + j] = run; run += v; }
     __syncthreads();
-    for (uint32_t cb = beg; cb < end; cb += kWave) {
-      const uint32_t i = cb + lane_id();
+#pragma unroll
+    for (int c = 0; c < kPL; c++) {
+      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
       const bool valid = i < end;
-      const uint64_t kv = valid ? ka[i] : 0ull;
-      const uint32_t dg = (uint32_t)((kv >> sh) & 255u);
+      const uint32_t dg = (uint32_t)((kv[c] >> sh) & 255u);
       uint64_t mk = __ballot(valid);
       for (int bt = 0; bt < 8; bt++) {
         const uint64_t bb = __ballot(valid && ((dg >> bt) & 1u));
@@ -147,8 +159,8 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
       if (valid) pos = s_cnt[dg * kMW + w] + rank;
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        kb[pos] = kv;
-        ib[pos] = ia[i];
+        kb[pos] = kv[c];
+        ib[pos] = iv[c];
         if (rank == cnt - 1) s_cnt[dg * kMW + w] += cnt;
       }
       __builtin_amdgcn_wave_barrier();
@@ -192,9 +204,19 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *key, uint64_t n
   const uint32_t kb = ctl->keybits;
   const int t = threadIdx.x, w = t / kWave;
   if (t == 0) { s_best = ~0ull; s_r = 0; }
+  // this thread's deltas, read once (kSeg / kMT of them)
+  constexpr int kPer = kSeg / kMT;
+  uint64_t dl[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t i = 1 + t + (uint32_t)j * kMT;
+    dl[j] = i < m ? key[base + i] - key[base + i - 1] : 0u;
+  }
   for (uint32_t r = 0; r <= kb; r++) {
     unsigned long long c = 0;
-    for (uint32_t i = 1 + t; i < m; i += kMT) c += rice_cost(key[base + i] - key[base + i - 1], r, kb);
+#pragma unroll
+    for (int j = 0; j < kPer; j++)
+      if (1 + t + (uint32_t)j * kMT < m) c += rice_cost(dl[j], r, kb);
     c = wave_sum(c);
     if (lane_id() == 0) s_sum[w] = c;
     __syncthreads();
