@@ -616,7 +616,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
 // counters of the slabs of every workgroup that visited the field (see
 // k_quant) to the wrap carries and out-of-window counts already there.
 // Grid: (largest window / 256, nslots, nf).
-__global__ __launch_bounds__(256) void k_hmerge(const CField *__restrict__ F, uint32_t nslots, uint32_t G,
+__global__ __launch_bounds__(256) void k_hmerge(const CField *__restrict__ F, uint32_t nslots, uint32_t QG,
                                                 const uint32_t *__restrict__ qmeta,
                                                 const uint32_t *__restrict__ slabs) {
   const int f = blockIdx.z;
@@ -626,13 +626,28 @@ __global__ __launch_bounds__(256) void k_hmerge(const CField *__restrict__ F, ui
   const QWin qw = qwin_of(nslots, slot);
   const uint32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= qw.size) return;
-  const uint32_t *visit_base = qmeta, *ffirst = qmeta + G + 1, *wf0 = qmeta + 2 * G + 1;
+  const uint32_t *visit_base = qmeta, *ffirst = qmeta + QG + 1, *wf0 = qmeta + 2 * QG + 1;
   const uint32_t *wf1 = wf0 + gridDim.z;
   const uint32_t k = qw.off + i, sh = (k & 1u) << 4;
+  // the visits of field f are workgroups w0..w1 in turn: w0's last visit,
+  // then one visit each, so their slabs are consecutive from w0's
+  const uint32_t w0 = wf0[f], w1 = min(wf1[f], QG - 1);
   uint32_t v = 0;
-  for (uint32_t w = wf0[f]; w <= wf1[f] && w < G; w++)
-    v += (slabs[(uint64_t)(visit_base[w] + (uint32_t)f - ffirst[w]) * kWinWords + (k >> 1)] >> sh) & 0xffffu;
-  c.hist[(uint64_t)slot * kNSyms + qw.base + i] += v;
+  if (w0 <= w1) {
+    const uint32_t nv = w1 - w0 + 1;
+    const gptr<const uint32_t> sp =
+        G(slabs) + (uint64_t)(visit_base[w0] + (uint32_t)f - ffirst[w0]) * kWinWords + (k >> 1);
+    uint32_t j = 0;
+    for (; j + 16 <= nv; j += 16) {  // sixteen slabs per round trip
+      uint32_t a[16];
+#pragma unroll
+      for (int u = 0; u < 16; u++) a[u] = sp[(uint64_t)(j + u) * kWinWords];
+#pragma unroll
+      for (int u = 0; u < 16; u++) v += (a[u] >> sh) & 0xffffu;
+    }
+    for (; j < nv; j++) v += (sp[(uint64_t)j * kWinWords] >> sh) & 0xffffu;
+  }
+  G(c.hist)[(uint64_t)slot * kNSyms + qw.base + i] += v;
 }
 
 // Training data of the selector: features, the three trial costs and the
