@@ -120,10 +120,12 @@ __global__ __launch_bounds__(kThreads) void k_params(const CField *__restrict__ 
   FState *st = c.st;
   const int t = threadIdx.x;
   uint32_t mn = 0xffffffffu, mx = 0u, bad = 0u;
+  const gptr<const uint32_t> bs = G(static_cast<const uint32_t *>(c.blkstat));
+#pragma unroll 8
   for (uint32_t b = t; b < c.nblocks; b += kThreads) {
-    mn = min(mn, c.blkstat[3 * b]);
-    mx = max(mx, c.blkstat[3 * b + 1]);
-    bad |= c.blkstat[3 * b + 2];
+    mn = min(mn, bs[3 * b]);
+    mx = max(mx, bs[3 * b + 1]);
+    bad |= bs[3 * b + 2];
   }
   s_mn[t] = mn; s_mx[t] = mx; s_bad[t] = bad;
   __syncthreads();

@@ -51,25 +51,30 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
   const int t = threadIdx.x;
   __shared__ int s_bad;
   __shared__ uint32_t s_tot[kPrepThreads / kWave][4];
+  // the header, read by 32 threads at once and parsed from LDS
+  __shared__ uint32_t s_hdr[kHdr / 4];
+  if (t < kHdr / 4) s_hdr[t] = df.in_len >= (uint64_t)kHdr ? rd32(G(in), 4ull * t) : 0u;
+  __syncthreads();
   if (t == 0) {
+    const uint8_t *hb = reinterpret_cast<const uint8_t *>(s_hdr);
     int bad = 0;
     st->status = 0;
     st->is_const = 0;
     st->multi = 0;
-    if (df.in_len < (uint64_t)kHdr || rd32(in, H_MAGIC) != kMagic || rd16(in, H_VERSION) != 1) bad = 1;
+    if (df.in_len < (uint64_t)kHdr || rd32(hb, H_MAGIC) != kMagic || rd16(hb, H_VERSION) != 1) bad = 1;
     uint32_t policy = 0, flags = 0, S = 0, nb = 0;
     uint64_t n = 0, total = 0;
     if (!bad) {
-      policy = in[H_POLICY];
-      flags = in[H_FLAGS];
-      n = rd64(in, H_N);
-      S = rd32(in, H_S);
-      nb = rd32(in, H_NB);
-      total = rd64(in, H_TOTAL);
+      policy = hb[H_POLICY];
+      flags = hb[H_FLAGS];
+      n = rd64(hb, H_N);
+      S = rd32(hb, H_S);
+      nb = rd32(hb, H_NB);
+      total = rd64(hb, H_TOTAL);
       if (policy > 3 || n != df.n || total > df.in_len || S < 1024 || S > smax || (S & (S - 1))) bad = 1;
     }
     st->policy = policy; st->S = S; st->n = n;
-    st->mn = __uint_as_float(bad ? 0u : rd32(in, H_MN));
+    st->mn = __uint_as_float(bad ? 0u : rd32(hb, H_MN));
     if (!bad && (flags & 1u)) {
       st->is_const = 1;
       st->nblocks = 0;
@@ -77,20 +82,20 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
       const uint64_t nbx = (n + S - 1) / S;
       if (nb != nbx || nb > df.nblocks_max || n == 0) bad = 1;
       Sections sec = sections_of(nb, (int)policy);
-      st->step = __longlong_as_double((long long)rd64(in, H_STEP));
-      st->off_pred = rd64(in, H_OFF_PRED);
-      st->off_pfirst = rd64(in, H_OFF_PFIRST);
-      st->off_cwords = rd64(in, H_OFF_CWORDS);
-      st->off_nesc = rd64(in, H_OFF_NESC);
-      const uint64_t off_books = rd64(in, H_OFF_BOOKS);
-      st->off_payload = rd64(in, H_OFF_PAYLOAD);
-      st->payload_words = rd64(in, H_PWORDS);
+      st->step = __longlong_as_double((long long)rd64(hb, H_STEP));
+      st->off_pred = rd64(hb, H_OFF_PRED);
+      st->off_pfirst = rd64(hb, H_OFF_PFIRST);
+      st->off_cwords = rd64(hb, H_OFF_CWORDS);
+      st->off_nesc = rd64(hb, H_OFF_NESC);
+      const uint64_t off_books = rd64(hb, H_OFF_BOOKS);
+      st->off_payload = rd64(hb, H_OFF_PAYLOAD);
+      st->payload_words = rd64(hb, H_PWORDS);
       if (st->off_pred != sec.pred || st->off_pfirst != sec.pfirst || st->off_cwords != sec.cwords ||
           st->off_nesc != sec.nesc || off_books != sec.books)
         bad = 1;
       uint64_t o = off_books;
       for (int k = 0; k < 3; k++) {
-        const uint32_t ns = rd32(in, H_NSYM + 4 * k), ml = in[H_MAXLEN + k];
+        const uint32_t ns = rd32(hb, H_NSYM + 4 * k), ml = hb[H_MAXLEN + k];
         st->nsym[k] = ns;
         st->maxlen[k] = ml;
         st->book_off[k] = o;
@@ -109,8 +114,11 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
     return;
   }
   if (st->is_const) return;
-  // block word offsets and predictor groups
+  // block word offsets and predictor groups (the state's fields in registers)
   const uint32_t nb = st->nblocks, policy = st->policy, S = st->S;
+  const uint64_t nval = st->n;
+  const uint32_t nsym[3] = {st->nsym[0], st->nsym[1], st->nsym[2]};
+  const uint32_t mlen[3] = {st->maxlen[0], st->maxlen[1], st->maxlen[2]};
   const uint32_t cwmax = S * kLMax / 32;
   const uint32_t per = (nb + kPrepThreads - 1) / kPrepThreads;
   const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
@@ -136,10 +144,10 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
       const uint32_t b = b0 + j;
       if (b >= hi) break;
       const uint32_t cw = cwv[j], ne = nev[j], k = kv[j];
-      const uint32_t blen = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
-      if (k > 2 || st->nsym[k] == 0 || cw > cwmax || ne > blen) { bad = 1; continue; }
+      const uint32_t blen = (uint32_t)min((uint64_t)S, nval - (uint64_t)b * S);
+      if (k > 2 || (k == 0 ? nsym[0] : k == 1 ? nsym[1] : nsym[2]) == 0 || cw > cwmax || ne > blen) { bad = 1; continue; }
       cnt[k]++;
-      words += skip_words(cw, st->maxlen[k]) + cw + ne;
+      words += skip_words(cw, k == 0 ? mlen[0] : k == 1 ? mlen[1] : mlen[2]) + cw + ne;
     }
   }
   // workgroup exclusive scans of (words, cnt0, cnt1, cnt2)
@@ -175,8 +183,10 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
       const uint32_t b = b0 + j;
       if (b >= hi) break;
       boff[b] = run;
-      run += skip_words(cwv[j], st->maxlen[kv[j]]) + cwv[j] + nev[j];
-      order[gpos[kv[j]]++] = b;
+      const uint32_t k = kv[j];
+      run += skip_words(cwv[j], k == 0 ? mlen[0] : k == 1 ? mlen[1] : mlen[2]) + cwv[j] + nev[j];
+      const uint32_t gp = k == 0 ? gpos[0]++ : k == 1 ? gpos[1]++ : gpos[2]++;
+      order[gp] = b;
     }
   }
   if (t == 0) {
@@ -198,11 +208,14 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
   const uint8_t *in = df.in;
   const uint32_t ns = st->nsym[k], ml = st->maxlen[k];
   const uint64_t bo = st->book_off[k];
+  // the per-length counts, read by ml threads at once
+  if (t < 32) s_cnt[t] = (t >= 1 && (uint32_t)t <= ml) ? rd32(G(in), bo + 4ull * (t - 1)) : 0u;
+  __syncthreads();
   if (t == 0) {
     uint32_t tot = 0, code = 0, idx = 0;
     int ok = 1;
-    for (int l = 0; l < 32; l++) { s_cnt[l] = 0; s_first[l] = 0; s_base[l] = 0; s_limit[l] = 0; }
-    for (uint32_t l = 1; l <= ml; l++) { s_cnt[l] = rd32(in, bo + 4ull * (l - 1)); tot += s_cnt[l]; }
+    for (int l = 0; l < 32; l++) { s_first[l] = 0; s_base[l] = 0; s_limit[l] = 0; }
+    for (uint32_t l = 1; l <= ml; l++) tot += s_cnt[l];
     if (tot != ns || s_cnt[ml] == 0) ok = 0;
     for (uint32_t l = 1; l <= ml && ok; l++) {
       s_first[l] = code;
