@@ -1198,6 +1198,8 @@ __global__ __launch_bounds__(kThreads) void k_books(const CField *__restrict__ F
 
 constexpr uint64_t kFlagAgg = 1ull << 62, kFlagPre = 2ull << 62, kValMask = (1ull << 62) - 1;
 
+constexpr int kEncWin = 2048;  // pack kernel: codewords held in LDS
+constexpr uint32_t kEncBase = 32768u - kEncWin / 2;
 template <int E>
 __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__ F, int nf,
                                                    const uint64_t *__restrict__ fb0, uint64_t total, GCtl *gc) {
@@ -1209,7 +1211,12 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
   __shared__ uint32_t s_g;
   __shared__ unsigned long long s_wtot[kThreads / kWave];
   __shared__ unsigned long long s_prefix;
+  // codewords of the codes around 32768 of the last (field, predictor)
+  // coded here, for fields long enough that a workgroup's successive tickets
+  // mostly fall in one field: most lookups then stay in LDS
+  __shared__ uint32_t s_enc[kEncWin];
   const int t = threadIdx.x, w = t / kWave;
+  int cur = -1;
 
   for (;;) {
     if (t == 0) s_g = atomicAdd(&gc->ticket, 1u);
@@ -1231,6 +1238,13 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
     const int slot = c.policy >= 2 ? pred : 0;
     const gptr<const uint32_t> enc = G(c.enc) + (uint64_t)slot * kNSyms;
+    const bool win = c.nblocks >= 2ull * gridDim.x;
+    if (win && f * 3 + slot != cur) {
+      // the previous block's lookups are behind this block's first barriers
+      for (uint32_t i = t; i < (uint32_t)kEncWin; i += kThreads) s_enc[i] = enc[kEncBase + i];
+      __syncthreads();
+      cur = f * 3 + slot;
+    }
 
     uint32_t cw[E];
     int32_t rr[E];
@@ -1241,7 +1255,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
       int32_t r = residual_at<E>(d, pv, e, pred);
       uint32_t q = (r > -kRadius && r < kRadius) ? (uint32_t)(r + kRadius) : 0u;
       rr[e] = r;
-      cw[e] = valid ? enc[q] : 0u;
+      cw[e] = !valid ? 0u : (win && q - kEncBase < (uint32_t)kEncWin ? s_enc[q - kEncBase] : enc[q]);
       bits += cw[e] >> 24;
       nesc += (valid && q == 0u) ? 1u : 0u;
     }
