@@ -1103,6 +1103,8 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
     // its lengths fit; the last to finish takes the first that fits
     uint64_t win = blockIdx.x;
     if (nvar > 1) {
+      // every thread's code lengths reach device scope before the count
+      __threadfence();
       __syncthreads();
       if (t == 0) {
         __hip_atomic_store(&gc->hres[blockIdx.x], built ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
