@@ -370,34 +370,24 @@ __device__ inline void block_trial(const int32_t (&d)[E], const int32_t (&pv)[3]
 //   10 #(Dp_j Dp_{j-1} < 0)/m   11 F(sum bitlen|Dp|) - F(m)
 //   12 F(sum bitlen|D2p|) - F(m)   13 #(|Dp|>=32768)/m   14 F(P')   15 1
 // with P' = max(P, 1), F = flog_u64 and every ratio one fp64 division
-// rounded to float.  Leaves the 16 features in s_feat.
+// rounded to float.  Threads 0..15 (wave 0) leave the 16 features in s_feat,
+// bfloat16-rounded if kRound, with no barrier after.
 constexpr int kFeatStride = 4;
-struct FeatRed {
-  long long sd[kThreads / kWave];
-  unsigned long long s1[kThreads / kWave], s2[kThreads / kWave];
-  int32_t dmx[kThreads / kWave], dmn[kThreads / kWave];
-  uint32_t m1[kThreads / kWave], m2[kThreads / kWave];
-  uint32_t zz[kThreads / kWave], oo[kThreads / kWave], se[kThreads / kWave];
-  uint32_t b1[kThreads / kWave], b2[kThreads / kWave];
+// Per-wave partials of the features, one 16-word record per wave, every
+// word combined over the waves by a 32-bit sum or maximum: the 64-bit sums
+// as (low 24 bits, signed rest) pairs, the signed extrema as unsigned maxima
+// of order-preserving images.
+enum : int { FR_SD = 0, FR_S1 = 2, FR_S2 = 4, FR_DMX = 6, FR_DMN = 7, FR_M1 = 8, FR_M2 = 9, FR_ZZ = 10,
+             FR_OO = 11, FR_SE = 12, FR_B1 = 13, FR_B2 = 14, FR_WORDS = 16 };
+struct alignas(16) FeatRed {
+  uint32_t w[kThreads / kWave][FR_WORDS];
 };
 
-template <typename T>
-__device__ inline T wave_max_t(T v) {
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) { T u = __shfl_xor(v, o, kWave); v = u > v ? u : v; }
-  return v;
-}
-template <typename T>
-__device__ inline T wave_min_t(T v) {
-#pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) { T u = __shfl_xor(v, o, kWave); v = u < v ? u : v; }
-  return v;
-}
-
-template <int E>
+template <int E, bool kRound>
 __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)[3], int32_t p0, uint32_t len,
                                       int64_t P, FeatRed *r, float *s_feat) {
   const int t = threadIdx.x, w = t / kWave;
+  const uint32_t lane = lane_id();
   long long sd = 0;
   unsigned long long s1 = 0, s2 = 0;
   int32_t dmx = INT32_MIN, dmn = INT32_MAX;
@@ -426,62 +416,87 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
       b2 += 32u - __clz(a2);
     }
   }
-  sd = wave_sum(sd);
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  dmx = wave_max_t(dmx);
-  dmn = wave_min_t(dmn);
-  m1 = wave_max_t(m1);
-  m2 = wave_max_t(m2);
-  zz = wave_sum(zz);
-  oo = wave_sum(oo);
-  se = wave_sum(se);
-  b1 = wave_sum(b1);
-  b2 = wave_sum(b2);
-  if ((t & (kWave - 1)) == 0) {
-    r->sd[w] = sd; r->s1[w] = s1; r->s2[w] = s2; r->dmx[w] = dmx; r->dmn[w] = dmn; r->m1[w] = m1; r->m2[w] = m2;
-    r->zz[w] = zz; r->oo[w] = oo; r->se[w] = se; r->b1[w] = b1; r->b2[w] = b2;
+  // wave totals with DPP lane moves (the two bit-length sums share a word;
+  // the paired counts stay below 2^16 over the whole block)
+  static_assert(E / kFeatStride * 32 * kWave < 65536, "bit-length sums share a word");
+  static_assert(E / kFeatStride * kThreads < 65536, "paired counts share a word");
+  const auto add = [](uint32_t a, uint32_t b) { return a + b; };
+  const auto umax = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  uint32_t rec[FR_WORDS];
+  rec[FR_SD] = wave_reduce_dpp((uint32_t)sd & 0xffffffu, add);
+  rec[FR_SD + 1] = wave_reduce_dpp((uint32_t)(sd >> 24), add);
+  rec[FR_S1] = wave_reduce_dpp((uint32_t)s1 & 0xffffffu, add);
+  rec[FR_S1 + 1] = wave_reduce_dpp((uint32_t)(s1 >> 24), add);
+  rec[FR_S2] = wave_reduce_dpp((uint32_t)s2 & 0xffffffu, add);
+  rec[FR_S2 + 1] = wave_reduce_dpp((uint32_t)(s2 >> 24), add);
+  rec[FR_DMX] = wave_reduce_dpp((uint32_t)dmx ^ 0x80000000u, umax);
+  rec[FR_DMN] = wave_reduce_dpp(~((uint32_t)dmn ^ 0x80000000u), umax);
+  rec[FR_M1] = wave_reduce_dpp(m1, umax);
+  rec[FR_M2] = wave_reduce_dpp(m2, umax);
+  rec[FR_ZZ] = wave_reduce_dpp(zz, add);
+  rec[FR_OO] = wave_reduce_dpp(oo, add);
+  rec[FR_SE] = wave_reduce_dpp(se, add);
+  const uint32_t bb = wave_reduce_dpp(b1 | (b2 << 16), add);
+  rec[FR_B1] = bb & 0xffffu;
+  rec[FR_B2] = bb >> 16;
+  rec[15] = 0;
+  if (lane == 0) {
+    uint4 *o = reinterpret_cast<uint4 *>(r->w[w]);
+#pragma unroll
+    for (int q = 0; q < FR_WORDS / 4; q++) o[q] = make_uint4(rec[4 * q], rec[4 * q + 1], rec[4 * q + 2], rec[4 * q + 3]);
   }
   __syncthreads();
-  // thread k < 16 finishes feature k: one numerator / denominator pair and
-  // one kind of formula each, so that a single division is in flight
-  if (t < kNFeat) {
-    for (int v = 1; v < kThreads / kWave; v++) {
-      sd += r->sd[v]; s1 += r->s1[v]; s2 += r->s2[v];
-      dmx = max(dmx, r->dmx[v]); dmn = min(dmn, r->dmn[v]);
-      m1 = max(m1, r->m1[v]); m2 = max(m2, r->m2[v]);
-      zz += r->zz[v]; oo += r->oo[v]; se += r->se[v]; b1 += r->b1[v]; b2 += r->b2[v];
+  if (w != 0) return;
+  // wave 0: lane l reads wave (l mod 4)'s record; two quad moves leave the
+  // block totals in every lane
+  {
+    const uint4 *in = reinterpret_cast<const uint4 *>(r->w[lane & 3u]);
+#pragma unroll
+    for (int q = 0; q < FR_WORDS / 4; q++) {
+      const uint4 v = in[q];
+      rec[4 * q] = v.x; rec[4 * q + 1] = v.y; rec[4 * q + 2] = v.z; rec[4 * q + 3] = v.w;
     }
-    const uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
-    const uint32_t m = (len + kFeatStride - 1) / kFeatStride;  // sampled positions
-    uint64_t a = 0, den = m;
-    int kind = 0;  // 0: a / den, 1: F(a) - F(m), 2: F(a), 3: one
-    switch (t) {
-      case 0: a = (uint64_t)(sd + (long long)m * (long long)p0); den = (uint64_t)m * Pp; break;
-      case 1: a = (uint64_t)((int64_t)dmx - (int64_t)dmn); den = Pp; break;
-      case 2: a = s1; kind = 1; break;
-      case 3: a = s2; kind = 1; break;
-      case 4: a = m1; kind = 2; break;
-      case 5: a = m2; kind = 2; break;
-      case 6: a = zz & 0xffffu; break;
-      case 7: a = zz >> 16; break;
-      case 8: a = oo & 0xffffu; break;
-      case 9: a = oo >> 16; break;
-      case 10: a = se & 0xffffu; break;
-      case 11: a = b1; kind = 1; break;
-      case 12: a = b2; kind = 1; break;
-      case 13: a = se >> 16; break;
-      case 14: a = Pp; kind = 2; break;
-      default: kind = 3; break;
-    }
-    float fv;
-    if (kind == 0) fv = __double2float_rn(__ddiv_rn((double)a, (double)den));
-    else if (kind == 1) fv = flog_u64(a) - flog_u64(m);
-    else if (kind == 2) fv = flog_u64(a);
-    else fv = 1.0f;
-    s_feat[t] = fv;
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < FR_WORDS - 1; k++) {
+    const bool mx = k >= FR_DMX && k <= FR_M2;
+    uint32_t x = rec[k];
+    uint32_t y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);  // quad_perm 1,0,3,2
+    x = mx ? (x > y ? x : y) : x + y;
+    y = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);  // quad_perm 2,3,0,1
+    rec[k] = mx ? (x > y ? x : y) : x + y;
+  }
+  const auto wide = [&](int k) { return (long long)(int32_t)rec[k + 1] * 16777216ll + (long long)rec[k]; };
+  // lane k < 16 finishes feature k: a numerator and a denominator, then one
+  // of four formulas, all chosen by selects
+  const uint64_t Pp = P > 0 ? (uint64_t)P : 1u;
+  const uint32_t m = (len + kFeatStride - 1) / kFeatStride;  // sampled positions
+  const int k = (int)lane;
+  const int64_t span = (int64_t)(int32_t)(rec[FR_DMX] ^ 0x80000000u) - (int64_t)(int32_t)(~rec[FR_DMN] ^ 0x80000000u);
+  uint64_t a = (uint64_t)(wide(FR_SD) + (long long)m * (long long)p0);
+  a = k == 1 ? (uint64_t)span : a;
+  a = k == 2 ? (uint64_t)wide(FR_S1) : a;
+  a = k == 3 ? (uint64_t)wide(FR_S2) : a;
+  a = k == 4 ? rec[FR_M1] : a;
+  a = k == 5 ? rec[FR_M2] : a;
+  a = k == 6 ? rec[FR_ZZ] & 0xffffu : a;
+  a = k == 7 ? rec[FR_ZZ] >> 16 : a;
+  a = k == 8 ? rec[FR_OO] & 0xffffu : a;
+  a = k == 9 ? rec[FR_OO] >> 16 : a;
+  a = k == 10 ? rec[FR_SE] & 0xffffu : a;
+  a = k == 11 ? rec[FR_B1] : a;
+  a = k == 12 ? rec[FR_B2] : a;
+  a = k == 13 ? rec[FR_SE] >> 16 : a;
+  a = k == 14 ? Pp : a;
+  const uint64_t den = k == 0 ? (uint64_t)m * Pp : k == 1 ? Pp : (uint64_t)m;
+  // kind: 0 a / den, 1 F(a) - F(m), 2 F(a), 3 one
+  constexpr uint32_t kKinds = (1u << 4) | (1u << 6) | (2u << 8) | (2u << 10) | (1u << 22) | (1u << 24) |
+                              (2u << 28) | (3u << 30);
+  const uint32_t kind = (kKinds >> (2 * (k & 15))) & 3u;
+  const float q = __double2float_rn(__ddiv_rn((double)a, (double)den));
+  const float fa = flog_u64(a);
+  const float fv = kind == 0 ? q : kind == 1 ? fa - flog_u64(m) : kind == 2 ? fa : 1.0f;
+  if (k < kNFeat) s_feat[k] = kRound ? bf16_round(fv) : fv;
 }
 
 // Adds v (<= 64) to 16-bit counter idx16 of the LDS window; a counter that
@@ -515,9 +530,9 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
   constexpr int S = E * kThreads;
   extern __shared__ uint32_t s_win[];
   // the selector's parameters, staged once per workgroup (learned policy)
-  __shared__ float s_mlp[kLearn ? kMlpParams : 1];
+  __shared__ __align__(16) float s_mlp[kLearn ? kMlpLds : 4];
   if (kLearn) {
-    for (int i = threadIdx.x; i < kMlpParams; i += kThreads) s_mlp[i] = sel[i];
+    for (int i = threadIdx.x; i < kMlpParams; i += kThreads) s_mlp[mlp_lds_slot(i)] = sel[i];
     __syncthreads();
   }
   __shared__ int32_t s_tail[3 * kThreads];
@@ -526,7 +541,8 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
   __shared__ int32_t s_p0;
   __shared__ int s_pred, s_fb;
   __shared__ FeatRed s_red;
-  __shared__ float s_feat[kNFeat];
+  __shared__ __align__(16) float s_feat[kNFeat];
+  __shared__ __align__(16) float s_h[kLearn ? 32 : 4];
   const int t = threadIdx.x;
   int cur = -1;
 
@@ -543,12 +559,23 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
 
   const uint64_t g_begin = (uint64_t)blockIdx.x * total / gridDim.x;
   const uint64_t g_end = ((uint64_t)blockIdx.x + 1) * total / gridDim.x;
-  // the values of block g + 1 are loaded while block g is processed
+  // The values of block g + 1 are loaded while block g's histogram is
+  // counted.  The load is issued once block g's predictor is chosen: waits
+  // for vector memory are in issue order, and the trial's table reads would
+  // otherwise wait for it.  A workgroup's blocks are consecutive, so the
+  // field of the next block comes from a cursor that only moves forward.
+  int fcur = g_begin < g_end ? find_field(fb0, nf, g_begin) : 0;
+  uint64_t fend = fcur + 1 < nf ? fb0[fcur + 1] : total;
+  int fn = fcur;  // field of the block in vn
   auto fetch = [&](uint64_t g, float (&v)[E]) {
-    const int f = find_field(fb0, nf, g);
-    const CField &c = F[f];
+    while (g >= fend) {
+      fcur++;
+      fend = fcur + 1 < nf ? fb0[fcur + 1] : total;
+    }
+    const CField &c = F[fcur];
     const uint64_t i0 = (g - c.gblock0) * S;
-    load_raw<E>(G(c.x) + i0, (uint32_t)min((uint64_t)S, c.n - i0), G(c.st)->mn, v);
+    load_raw<E>(G(c.x) + i0, (uint32_t)min((uint64_t)S, c.n - i0), K(static_cast<const FState *>(c.st))->mn, v);
+    fn = fcur;
   };
   float vn[E];
   if (g_begin < g_end) fetch(g_begin, vn);
@@ -556,11 +583,14 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     float v[E];
 #pragma unroll
     for (int e = 0; e < E; e++) v[e] = vn[e];
-    if (g + 1 < g_end) fetch(g + 1, vn);
-    const int f = find_field(fb0, nf, g);
+    const int f = fn;
     const CField &c = F[f];
-    const gptr<const FState> st = G(static_cast<const FState *>(c.st));
-    if (st->status != 0 || st->is_const) continue;
+    // per-field parameters through the scalar cache
+    const cptr<FState> st = K(static_cast<const FState *>(c.st));
+    if (st->status != 0 || st->is_const) {
+      if (g + 1 < g_end) fetch(g + 1, vn);
+      continue;
+    }
     if (f != cur) { flush(cur); cur = f; }
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b * S;
@@ -572,10 +602,10 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     if (c.policy >= 2) {
       bool trial = true;
       if (kLearn && c.policy == 3) {
-        block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
-        if (t < kWave) {
+        block_features<E, true>(d, pv, p0, len, st->P, &s_red, s_feat);
+        if (t < kWave) {  // wave 0 wrote the features
           float margin, z[3];
-          const int top = mlp_select_wave(s_mlp, s_feat, margin, z);
+          const int top = mlp_select_wave(s_mlp, s_feat, s_h, margin, z);
           if (t == 0) {
             s_pred = top;
             s_fb = !(margin >= c.tau);
@@ -590,6 +620,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
       if (t == 0) G(c.out)[c.sec.pred + b] = (uint8_t)pred;
     }
     if (t == 0) reinterpret_cast<gptr<int32_t>>(G(c.out) + c.sec.pfirst)[b] = p0;
+    if (g + 1 < g_end) fetch(g + 1, vn);
 
     // code histogram of the chosen predictor
     const int slot = c.policy >= 2 ? pred : 0;
@@ -671,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
   for (uint64_t g = blockIdx.x; g < total; g += gridDim.x) {
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
-    const gptr<const FState> st = G(static_cast<const FState *>(c.st));
+    const cptr<FState> st = K(static_cast<const FState *>(c.st));
     if (st->status != 0 || st->is_const) {
       if (t < kNFeat) feat[g * kNFeat + t] = 0.0f;
       if (t < 3) cost[g * 3 + t] = 0;
@@ -683,7 +714,7 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
     int32_t d[E], pv[3], p0;
     load_block_d<E>(c, st->mn, st->inv, i0, len, d, pv, s_tail, p0, &s_p0);
-    block_features<E>(d, pv, p0, len, st->P, &s_red, s_feat);
+    block_features<E, false>(d, pv, p0, len, st->P, &s_red, s_feat);
     block_trial<E>(d, pv, len, logt, s_cls, s_cost, &s_pred);
     if (t < kNFeat) feat[g * kNFeat + t] = s_feat[t];
     if (t < 3) cost[g * 3 + t] = s_cost[t];

@@ -57,6 +57,12 @@ __device__ __forceinline__ gptr<T> G(T *p) {
   return (gptr<T>)p;
 }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// Read-only view through the scalar data cache (constant address space),
+// for per-field parameters that nothing writes while the reading kernel
+// runs.  Uniform loads through it are scalar loads, counted apart from
+// vector memory, so waiting for them does not wait for data loads in flight.
+template <class T> using cptr = const T __attribute__((address_space(4))) *;
+template <class T> __device__ __forceinline__ cptr<T> K(const T *p) { return (cptr<T>)p; }
 
 // Section offsets that depend only on the block count and the policy.
 struct Sections {
@@ -215,29 +221,75 @@ __device__ inline float flog_u64(uint64_t v) {
   return (float)b + (float)frac * (1.0f / 256.0f);
 }
 
+// Copy of the parameters in LDS for the wave inference below: each weight
+// matrix output-major with its rows padded to 20 (W1) and 36 (W2, W3)
+// words, so that one 128-bit read gives a lane four consecutive weights of
+// its output and the lanes of a read fall on distinct banks.
+constexpr int kR1 = 20, kR2 = 36;
+constexpr int kL1 = 0, kLB1 = kL1 + 32 * kR1, kL2 = kLB1 + 32, kLB2 = kL2 + 32 * kR2, kL3 = kLB2 + 32,
+              kLB3 = kL3 + 3 * kR2, kMlpLds = kLB3 + 4;
+static_assert(kL2 % 4 == 0 && kL3 % 4 == 0, "rows start on 16-byte boundaries");
+__device__ inline int mlp_lds_slot(int i) {
+  if (i < kB1) return kL1 + (i / 16) * kR1 + i % 16;
+  if (i < kW2) return kLB1 + (i - kB1);
+  if (i < kB2) return kL2 + ((i - kW2) / 32) * kR2 + (i - kW2) % 32;
+  if (i < kW3) return kLB2 + (i - kB2);
+  if (i < kB3) return kL3 + ((i - kW3) / 32) * kR2 + (i - kW3) % 32;
+  return kLB3 + (i - kB3);
+}
+
+// Orders the LDS accesses of one wave around it (a wave's LDS operations
+// are executed in issue order; this keeps the compiler from moving them).
+__device__ inline void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inference on one block's features by one whole wave (lanes j and j + 32
-// both compute neuron j).  w: parameters with bfloat16-rounded weights and
-// float32 biases.  Each neuron starts from its bias and adds w_k x_k for k
+// both compute neuron j).  wl: the LDS copy above, bfloat16-rounded weights
+// and float32 biases; xb: the 16 features, already bfloat16-rounded, in LDS;
+// s_h: 32 floats of LDS that only this wave uses (the hidden layers pass
+// through it).  Each neuron starts from its bias and adds w_k x_k for k
 // ascending, one fused multiply-add each; hidden outputs are ReLU'd and
 // bfloat16-rounded.  Returns the argmax (ties to the lowest index) and the
-// margin to the runner-up, uniform over the wave.
-__device__ inline int mlp_select_wave(const float *__restrict__ w, const float *feat, float &margin,
+// margin to the runner-up, uniform over the wave.  xb, wl and s_h are
+// 16-byte aligned.
+__device__ inline int mlp_select_wave(const float *__restrict__ wl, const float *xb, float *s_h, float &margin,
                                       float (&z_out)[3]) {
-  const int j = (int)(__lane_id() & 31u);
-  float acc = w[kB1 + j];
+  const uint32_t lane = __lane_id();
+  const int j = (int)(lane & 31u);
+  const f32x4 *x4 = reinterpret_cast<const f32x4 *>(xb);
+  const f32x4 *h4 = reinterpret_cast<const f32x4 *>(s_h);
+  // sixteen terms per step: the reads of a step are issued together, steps
+  // are kept apart so that no more than 32 registers hold operands
+  const auto dot = [](float acc, const f32x4 *w, const f32x4 *x, int nq) {
 #pragma unroll
-  for (int k = 0; k < kNFeat; k++) acc = __builtin_fmaf(w[kW1 + 16 * j + k], bf16_round(feat[k]), acc);
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+      if (q0) wave_lds_order();
+#pragma unroll
+      for (int q = q0; q < q0 + 4; q++) {
+        const f32x4 a = w[q], b = x[q];
+        acc = __builtin_fmaf(a.x, b.x, acc);
+        acc = __builtin_fmaf(a.y, b.y, acc);
+        acc = __builtin_fmaf(a.z, b.z, acc);
+        acc = __builtin_fmaf(a.w, b.w, acc);
+      }
+    }
+    return acc;
+  };
+  wave_lds_order();
+  float acc = dot(wl[kLB1 + j], reinterpret_cast<const f32x4 *>(wl + kL1 + kR1 * j), x4, 4);
   const float h1 = bf16_round(acc > 0.0f ? acc : 0.0f);
-  acc = w[kB2 + j];
-#pragma unroll 8
-  for (int k = 0; k < 32; k++)
-    acc = __builtin_fmaf(w[kW2 + 32 * j + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), k)), acc);
+  if (lane < 32u) s_h[j] = h1;
+  wave_lds_order();
+  acc = dot(wl[kLB2 + j], reinterpret_cast<const f32x4 *>(wl + kL2 + kR2 * j), h4, 8);
   const float h2 = bf16_round(acc > 0.0f ? acc : 0.0f);
+  wave_lds_order();
+  if (lane < 32u) s_h[j] = h2;
+  wave_lds_order();
   const int jj = j < 3 ? j : 0;
-  acc = w[kB3 + jj];
-#pragma unroll 8
-  for (int k = 0; k < 32; k++)
-    acc = __builtin_fmaf(w[kW3 + 32 * jj + k], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h2), k)), acc);
+  acc = dot(wl[kLB3 + jj], reinterpret_cast<const f32x4 *>(wl + kL3 + kR2 * jj), h4, 8);
   float z[3];
 #pragma unroll
   for (int k = 0; k < 3; k++) z[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k));
@@ -287,6 +339,19 @@ __device__ inline uint32_t wave_scan_dpp(uint32_t x) {
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
   x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
   return x;
+}
+
+// Wave64 total under op with the same lane moves (op's identity must be 0,
+// which the moves shift in); read from lane 63, uniform over the wave.
+template <class Op>
+__device__ inline uint32_t wave_reduce_dpp(uint32_t x, Op op) {
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false));
+  x = op(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 template <typename T>

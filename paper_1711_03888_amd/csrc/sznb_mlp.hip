@@ -161,16 +161,21 @@ __global__ __launch_bounds__(kMlpThreads) void mlp_adam(float *__restrict__ w, f
 __global__ __launch_bounds__(kMlpThreads) void mlp_infer(const float *__restrict__ w, const float *__restrict__ feat,
                                                          uint64_t nb, float *__restrict__ logits,
                                                          uint8_t *__restrict__ choice, float *__restrict__ margin) {
-  __shared__ float s_w[kMlpParams];
+  __shared__ __align__(16) float s_w[kMlpLds];
+  __shared__ __align__(16) float s_x[kMlpThreads / kWave][kNFeat];
+  __shared__ __align__(16) float s_h[kMlpThreads / kWave][32];
   for (int i = threadIdx.x; i < kMlpParams; i += kMlpThreads) {
     const bool bias = (i >= kB1 && i < kW2) || (i >= kB2 && i < kW3) || i >= kB3;
-    s_w[i] = bias ? w[i] : bf16_round(w[i]);
+    s_w[mlp_lds_slot(i)] = bias ? w[i] : bf16_round(w[i]);
   }
   __syncthreads();
   const uint64_t waves = (uint64_t)gridDim.x * (kMlpThreads / kWave);
   for (uint64_t b = (uint64_t)blockIdx.x * (kMlpThreads / kWave) + threadIdx.x / kWave; b < nb; b += waves) {
+    const int w = threadIdx.x / kWave;
+    wave_lds_order();  // the previous block's reads of s_x are done
+    if (__lane_id() < (uint32_t)kNFeat) s_x[w][__lane_id()] = bf16_round(feat[b * kNFeat + __lane_id()]);
     float mg, z[3];
-    const int top = mlp_select_wave(s_w, feat + b * kNFeat, mg, z);
+    const int top = mlp_select_wave(s_w, s_x[w], s_h[w], mg, z);
     if (__lane_id() == 0) {
       choice[b] = (uint8_t)top;
       margin[b] = mg;
