@@ -587,7 +587,7 @@ __global__ __launch_bounds__(kThreads, kLearn ? 4 : 5) void k_quant(const CField
     const CField &c = F[f];
     // per-field parameters through the scalar cache
     const cptr<FState> st = K(static_cast<const FState *>(c.st));
-    if (st->status != 0 || st->is_const) {
+    if ((st->status != 0) | (st->is_const != 0)) {
       if (g + 1 < g_end) fetch(g + 1, vn);
       continue;
     }
@@ -1260,11 +1260,17 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     const int f = find_field(fb0, nf, g);
     const CField &c = F[f];
     const gptr<FState> st = G(c.st);
-    if (st->status != 0 || st->is_const) continue;
+    // The status is read through the scalar cache, so that no vector-memory
+    // wait precedes the block's loads.  A field is skipped only for a status
+    // set before this kernel: every block of a field that runs out of space
+    // here still publishes its look-back value (later blocks of the field
+    // wait for it); it only stores nothing.
+    const cptr<FState> sk = K(static_cast<const FState *>(c.st));
+    const int32_t status = sk->status;
+    if ((status != 0 && status != SZNB_ENOSPC) | (sk->is_const != 0)) continue;
     const uint64_t b = g - c.gblock0;
     const uint64_t i0 = b * S;
     const uint32_t len = (uint32_t)min((uint64_t)S, c.n - i0);
-    // the block's predictor is read along with its values
     const gptr<uint8_t> out = G(c.out);
     const int pred = c.policy >= 2 ? (int)out[c.sec.pred + b] : (int)c.policy;
     int32_t d[E], pv[3], p0;

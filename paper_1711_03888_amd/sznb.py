@@ -113,6 +113,10 @@ def compress_bound(n: int, mode: int) -> int:
     return int(lib().sznb_compress_bound(n, mode))
 
 
+def compress_min_capacity(n: int, mode: int) -> int:
+    return int(lib().sznb_compress_min_capacity(n, mode))
+
+
 def compress_workspace_bytes(ns: Sequence[int], modes: Sequence[int]) -> int:
     return int(lib().sznb_compress_workspace_bytes(len(ns), _arr(_u64, ns), _arr(ctypes.c_uint32, modes)))
 
