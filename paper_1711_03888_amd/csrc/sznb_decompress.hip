@@ -452,10 +452,22 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   uint32_t invalid = 0;
 
   // bring the block's words into cache with a coalesced sweep, so that the
-  // lanes' sequential readers below do not each wait on memory
+  // lanes' sequential readers below do not each wait on memory; sixteen
+  // loads per lane are issued before the first wait (a typical block is one
+  // round trip)
   {
+    const uint32_t nw = skw + cw;
     uint32_t sink = 0;
-    for (uint32_t i = l; i < skw + cw; i += kWave) sink |= sk[i];
+    for (uint32_t i0 = 0; i0 < nw; i0 += 16u * kWave) {
+      uint32_t a[16];
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWave + l;
+        a[u] = i < nw ? sk[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; u++) sink |= a[u];
+    }
     asm volatile("" ::"v"(sink));  // the loaded values count as used
   }
   // this lane's range and its first codeword
