@@ -559,37 +559,49 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   const double step = st->step, mn = (double)st->mn;
   const gptr<float> out = G(df.out) + (uint64_t)b * S;
   if (l == 0 && len && q16[0] != (uint16_t)kRadius) invalid = 1;
-  for (uint32_t row = 0; row < len; row += kWave) {
-    const uint32_t el = row + l;
-    const bool valid = el < len;
-    const uint32_t q = valid ? q16[qaddr(el)] : (uint32_t)kRadius;
-    uint32_t r = q - (uint32_t)kRadius;
-    const uint64_t em = __ballot(valid && q == 0u);
-    if (em) {
-      if (valid && q == 0u) {
-        const uint32_t ei = ebase + (uint32_t)__popcll(em & lt);
-        r = ei < ne ? esc[ei] : 0u;
+  // four rows per step: their scans are independent until the carries,
+  // which are added row by row afterwards (integer sums, so the grouping
+  // does not change them)
+  constexpr int kRows = 4;
+  const auto level = [](uint32_t (&v)[kRows], uint32_t &carry) {
+    uint32_t sc[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; u++) sc[u] = wave_scan_dpp(v[u]);
+#pragma unroll
+    for (int u = 0; u < kRows; u++) {
+      v[u] = sc[u] + carry;
+      carry += (uint32_t)__builtin_amdgcn_readlane((int)sc[u], 63);
+    }
+  };
+  for (uint32_t row0 = 0; row0 < len; row0 += kRows * kWave) {
+    uint32_t r[kRows];
+    uint64_t em[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; u++) {
+      const uint32_t el = row0 + (uint32_t)u * kWave + l;
+      const uint32_t q = el < len ? q16[qaddr(el)] : (uint32_t)kRadius;
+      r[u] = q - (uint32_t)kRadius;
+      em[u] = __ballot(el < len && q == 0u);
+    }
+    // escapes take their values in element order
+#pragma unroll
+    for (int u = 0; u < kRows; u++) {
+      if (em[u]) {
+        if ((em[u] >> l) & 1ull) {
+          const uint32_t ei = ebase + (uint32_t)__popcll(em[u] & lt);
+          r[u] = ei < ne ? esc[ei] : 0u;
+        }
+        ebase += (uint32_t)__popcll(em[u]);
       }
-      ebase += (uint32_t)__popcll(em);
     }
-    uint32_t x;
-    if (k == 0) {
-      x = wave_scan_dpp(r) + c0;
-      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-    } else if (k == 1) {
-      const uint32_t y = wave_scan_dpp(r) + c1;
-      c1 = (uint32_t)__builtin_amdgcn_readlane((int)y, 63);
-      x = wave_scan_dpp(y) + c0;
-      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
-    } else {
-      const uint32_t z = wave_scan_dpp(r) + c2;
-      c2 = (uint32_t)__builtin_amdgcn_readlane((int)z, 63);
-      const uint32_t y = wave_scan_dpp(z) + c1;
-      c1 = (uint32_t)__builtin_amdgcn_readlane((int)y, 63);
-      x = wave_scan_dpp(y) + c0;
-      c0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+    if (k >= 2) level(r, c2);
+    if (k >= 1) level(r, c1);
+    level(r, c0);
+#pragma unroll
+    for (int u = 0; u < kRows; u++) {
+      const uint32_t el = row0 + (uint32_t)u * kWave + l;
+      if (el < len) out[el] = (float)fma((double)(int32_t)((uint32_t)p0 + r[u]), step, mn);
     }
-    if (valid) out[el] = (float)fma((double)(int32_t)((uint32_t)p0 + x), step, mn);
   }
   if (ebase != ne) invalid = 1;
   if (__ballot(invalid)) { if (l == 0) *bad_flag = 1; }

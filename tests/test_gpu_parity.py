@@ -45,6 +45,23 @@ def _check(x, eb, mode, label=""):
 POLICIES = [sznb.PRED_LV, sznb.PRED_LCF, sznb.PRED_BESTFIT]
 
 
+def _three_predictor_field():
+    """A fast sine (QCF wins), a random walk (LV) and a slower sine (LCF at
+    eb_rel 1e-4), with ragged ends."""
+    t = np.arange(3 * 4096 + 1500, dtype=np.float64)
+    return np.concatenate([(1000 * np.sin(t / 20.0)).astype(np.float32), datagen.random_walk(2 * 4096, seed=21),
+                           (1000 * np.sin(np.arange(2 * 4096 + 333) / 100.0)).astype(np.float32)])
+
+
+@pytest.mark.parametrize("eb_rel", [1e-4, 1e-5])
+def test_all_three_predictors(eb_rel):
+    x = _three_predictor_field()
+    preds, _ = oracle.select(oracle.lattice(x, eb_rel), 4096)
+    assert 0 in preds and 2 in preds
+    print("three predictors eb=%g choices %s" % (eb_rel, preds.tolist()), flush=True)
+    _check(x, eb_rel, sznb.PRED_BESTFIT | sznb.EB_REL, "three predictors")
+
+
 @pytest.mark.parametrize("policy", POLICIES)
 @pytest.mark.parametrize("eb_rel", [1e-3, 1e-4])
 def test_walk_ragged(policy, eb_rel):
