@@ -32,7 +32,7 @@ def _fields():
             (datagen.md_lattice(cells=(8, 8, 16), seed=4)["zz"], 1e-3)]
 
 
-@pytest.mark.parametrize("S_log2", [10, 12])
+@pytest.mark.parametrize("S_log2", [10, 12, 14])
 def test_features_costs_labels_bitexact(S_log2):
     S = 1 << S_log2
     fields = _fields()
@@ -67,14 +67,15 @@ def test_inference_bitexact():
     assert np.array_equal(choice.cpu().numpy(), np.argmax(ref, axis=1))
 
 
-@pytest.mark.parametrize("tau", [float("-inf"), 0.0, 1.5, float("inf")])
-def test_learned_streams_bitexact(tau):
+@pytest.mark.parametrize("tau,S_log2", [(float("-inf"), 10), (0.0, 10), (1.5, 10), (float("inf"), 10),
+                                         (0.0, 14), (1.5, 12)])
+def test_learned_streams_bitexact(tau, S_log2):
     rng = np.random.default_rng(23)
     w = rng.normal(0, 0.5, mlp.NPARAM).astype(np.float32)
     sznb.set_selector(w, tau)
-    mode = sznb.PRED_LEARNED | sznb.EB_REL | sznb.BLOCK_LOG2(10)
+    mode = sznb.PRED_LEARNED | sznb.EB_REL | sznb.BLOCK_LOG2(S_log2)
     for i, (x, eb) in enumerate(_fields()):
-        print("learned tau=%g field %d" % (tau, i), flush=True)
+        print("learned tau=%g S=2^%d field %d" % (tau, S_log2, i), flush=True)
         ref = oracle.compress(x, eb, mode, selector=(w, tau))
         xt = _dev(np.ascontiguousarray(x, np.float32))
         outs = sznb.compress_batch([xt], eb, mode)
@@ -84,7 +85,7 @@ def test_learned_streams_bitexact(tau):
     # fallback counts equal the oracle's
     x, eb = _fields()[0]
     q = oracle.lattice(x, eb)
-    _, fb = oracle.select_learned(q, 1024, oracle.params(x, eb)["P"], w, tau)
+    _, fb = oracle.select_learned(q, 1 << S_log2, oracle.params(x, eb)["P"], w, tau)
     c = sznb.compress_batch_async([_dev(np.ascontiguousarray(x, np.float32))], eb, mode)
     assert sznb.compress_fallbacks(c.ws, 1) == [int(fb.sum())]
 
