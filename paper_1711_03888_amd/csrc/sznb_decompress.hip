@@ -646,7 +646,20 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     if (pair != cur) {
       __syncthreads();
       const gptr<const uint32_t> gl = G(df.lut) + (uint64_t)k * (2u << kLutBits);
-      for (uint32_t i = t; i < lut_words; i += blockDim.x) s_lut[i] = gl[i];
+      // eight loads per thread in flight before they are stored
+      for (uint32_t i0 = 0; i0 < lut_words; i0 += 8u * blockDim.x) {
+        uint32_t a[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const uint32_t i = i0 + (uint32_t)u * blockDim.x + t;
+          a[u] = i < lut_words ? gl[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const uint32_t i = i0 + (uint32_t)u * blockDim.x + t;
+          if (i < lut_words) s_lut[i] = a[u];
+        }
+      }
       const gptr<const uint32_t> gs = G(df.slow) + (uint64_t)k * kSlowWords;
       for (uint32_t i = t; i < 32u; i += blockDim.x) {
         s_first[i] = gs[i];

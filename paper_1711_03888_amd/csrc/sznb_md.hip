@@ -419,12 +419,25 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   // as zero; a read that would pass nbits marks the segment corrupt.
   const gptr<const uint32_t> gw = G(wp);
   const uint64_t nw = (nbits + 31) / 32;
-  // the segment's words are staged in LDS when they fit (one coalesced
-  // sweep; both passes then refill from LDS)
+  // the segment's words are staged in LDS when they fit (coalesced, sixteen
+  // loads per lane in flight before they are stored; both passes then
+  // refill from LDS)
   __shared__ uint32_t s_seg[kCpcLdsWords];
   const bool in_lds = !bad && nw <= kCpcLdsWords;
   if (in_lds)
-    for (uint32_t i = lane; i < nw; i += kWave) s_seg[i] = gw[i];
+    for (uint32_t i0 = 0; i0 < nw; i0 += 16u * kWave) {
+      uint32_t a[16];
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+        a[u] = i < nw ? gw[i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; u++) {
+        const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+        if (i < nw) s_seg[i] = a[u];
+      }
+    }
   __syncthreads();
   auto word = [&](uint64_t i) -> uint32_t { return i >= nw ? 0u : (in_lds ? s_seg[i] : gw[i]); };
   uint64_t pos = 0, buf = 0, wi = 0;
