@@ -19,6 +19,8 @@
 //   cpc_decode  one wave per segment, one lane per 256 keys (entry points
 //               stored in the stream): keys back, then lattice values
 //   md_assemble container header and sub-stream copies
+#include <type_traits>
+
 #include "sznb_internal.h"
 
 namespace sznb {
@@ -401,7 +403,7 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
     const uint64_t hi = *reinterpret_cast<const uint32_t *>(cs + 80 + 8 * c);
     step[c] = __longlong_as_double((long long)(lo | (hi << 32)));
   }
-  const uint32_t *sb = reinterpret_cast<const uint32_t *>(cs + kCpHdr);
+  const gptr<const uint32_t> sb = G(reinterpret_cast<const uint32_t *>(cs + kCpHdr));
   uint64_t woff = 0;
   for (uint32_t s = lane; s < seg; s += kWave) woff += (sb[s] + 31) / 32;
   woff = wave_sum(woff);
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
   const uint64_t avail = (cs_len - tab) / 4;
   bool bad = woff + (nbits + 31) / 32 > avail;
   const uint32_t *wp = reinterpret_cast<const uint32_t *>(cs + tab) + woff;
-  const uint32_t *ent = reinterpret_cast<const uint32_t *>(cs + etab) + (uint64_t)seg * (kSeg / kSub);
+  const gptr<const uint32_t> ent = G(reinterpret_cast<const uint32_t *>(cs + etab)) + (uint64_t)seg * (kSeg / kSub);
   const uint64_t base = (uint64_t)seg * kSeg;
   const uint32_t m = (uint32_t)min((uint64_t)kSeg, n - base);
   const uint32_t k0 = lane * kSub, k1 = min(m, k0 + kSub);  // this lane's keys
@@ -439,89 +441,99 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *cs, uint64_t 
       }
     }
   __syncthreads();
-  auto word = [&](uint64_t i) -> uint32_t { return i >= nw ? 0u : (in_lds ? s_seg[i] : gw[i]); };
-  uint64_t pos = 0, buf = 0, wi = 0;
-  uint32_t nv = 0;
-  auto seek = [&](uint64_t p) {
-    pos = p;
-    wi = p >> 5;
-    const uint32_t sh = (uint32_t)(p & 31u);
-    const uint64_t w0 = word(wi), w1 = word(wi + 1);
-    buf = ((w0 << 32) | w1) << sh;
-    nv = 64u - sh;
-    wi += 2;
-  };
-  auto skip = [&](uint32_t nb) {  // nb <= 32
-    buf = nb ? buf << nb : buf;
-    nv -= nb;
-    pos += nb;
-    if (nv <= 32u) {
-      buf |= (uint64_t)word(wi) << (32u - nv);
-      nv += 32u;
-      wi++;
+  // The bit reader refills from LDS or from global memory, decided once per
+  // segment: a refill that could take either path made the compiler wait
+  // for every vector-memory operation in flight (pass 2's stores) at each
+  // refill.
+  const auto run = [&](auto lds) {
+    constexpr bool kL = decltype(lds)::value;
+    auto word = [&](uint64_t i) -> uint32_t { return i >= nw ? 0u : (kL ? s_seg[i] : gw[i]); };
+    uint64_t pos = 0, buf = 0, wi = 0;
+    uint32_t nv = 0;
+    auto seek = [&](uint64_t p) {
+      pos = p;
+      wi = p >> 5;
+      const uint32_t sh = (uint32_t)(p & 31u);
+      const uint64_t w0 = word(wi), w1 = word(wi + 1);
+      buf = ((w0 << 32) | w1) << sh;
+      nv = 64u - sh;
+      wi += 2;
+    };
+    auto skip = [&](uint32_t nb) {  // nb <= 32
+      buf = nb ? buf << nb : buf;
+      nv -= nb;
+      pos += nb;
+      if (nv <= 32u) {
+        buf |= (uint64_t)word(wi) << (32u - nv);
+        nv += 32u;
+        wi++;
+      }
+    };
+    auto take = [&](uint32_t nb) -> uint64_t {  // nb <= 32
+      if (!nb) return 0;
+      if (pos + nb > nbits) { bad = true; return 0; }
+      const uint64_t v = buf >> (64u - nb);
+      skip(nb);
+      return v;
+    };
+    auto take_wide = [&](uint32_t nb) -> uint64_t {
+      if (nb > 32u) { const uint64_t hi = take(nb - 32u); return (hi << 32) | take(32u); }
+      return take(nb);
+    };
+    // the Rice parameter follows the first key
+    uint32_t r = 0;
+    if (!bad) {
+      seek(kb);
+      r = (uint32_t)take(6);
+      if (r > kb) bad = true;
+    }
+    const uint64_t start = active ? ent[lane] : 0;
+    const uint64_t stop = (k1 < m) ? ent[lane + 1] : nbits;
+    if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
+    auto next = [&](uint32_t i) -> uint64_t {  // delta of key i (the raw key for i = 0)
+      if (i == 0) { const uint64_t k = take_wide(kb); (void)take(6); return k; }
+      // unary quotient: the ones before the first zero, at most kEscQ (= 32)
+      const uint32_t ones = ~(uint32_t)(buf >> 32);
+      const uint32_t q = ones ? (uint32_t)__clz(ones) : kEscQ;
+      const uint32_t ub = q < kEscQ ? q + 1u : kEscQ;
+      if (pos + ub > nbits) { bad = true; return 0; }
+      skip(ub);
+      if (q == kEscQ) return take_wide(kb);
+      return ((uint64_t)q << r) | take_wide(r);
+    };
+    // pass 1: sum of this lane's deltas
+    uint64_t sum = 0;
+    if (active && !bad) {
+      seek(start);
+      for (uint32_t i = k0; i < k1 && !bad; i++) sum += next(i);
+      if (pos != stop) bad = true;
+    }
+    // exclusive prefix of the lane sums
+    uint64_t inc = sum;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint64_t o = __shfl_up(inc, d, kWave);
+      if ((int)lane >= d) inc += o;
+    }
+    const bool any_bad = __ballot(bad) != 0;
+    if (any_bad) {
+      if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+      return;
+    }
+    // pass 2: keys and coordinates (global stores: flat stores in flight
+    // would hold up every LDS refill of the bit reader)
+    if (!active) return;
+    uint64_t k = inc - sum;
+    seek(start);
+    const gptr<float> gx = G(ox), gy = G(oy), gz = G(oz);
+    for (uint32_t i = k0; i < k1; i++) {
+      k += next(i);
+      const uint32_t px = compact3(k >> 2), py = compact3(k >> 1), pz = compact3(k);
+      gx[base + i] = (float)fma((double)(int32_t)px, step[0], (double)mn[0]);
+      gy[base + i] = (float)fma((double)(int32_t)py, step[1], (double)mn[1]);
+      gz[base + i] = (float)fma((double)(int32_t)pz, step[2], (double)mn[2]);
     }
   };
-  auto take = [&](uint32_t nb) -> uint64_t {  // nb <= 32
-    if (!nb) return 0;
-    if (pos + nb > nbits) { bad = true; return 0; }
-    const uint64_t v = buf >> (64u - nb);
-    skip(nb);
-    return v;
-  };
-  auto take_wide = [&](uint32_t nb) -> uint64_t {
-    if (nb > 32u) { const uint64_t hi = take(nb - 32u); return (hi << 32) | take(32u); }
-    return take(nb);
-  };
-  // the Rice parameter follows the first key
-  uint32_t r = 0;
-  if (!bad) {
-    seek(kb);
-    r = (uint32_t)take(6);
-    if (r > kb) bad = true;
-  }
-  const uint64_t start = active ? ent[lane] : 0;
-  const uint64_t stop = (k1 < m) ? ent[lane + 1] : nbits;
-  if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
-  auto next = [&](uint32_t i) -> uint64_t {  // delta of key i (the raw key for i = 0)
-    if (i == 0) { const uint64_t k = take_wide(kb); (void)take(6); return k; }
-    // unary quotient: the ones before the first zero, at most kEscQ (= 32)
-    const uint32_t ones = ~(uint32_t)(buf >> 32);
-    const uint32_t q = ones ? (uint32_t)__clz(ones) : kEscQ;
-    const uint32_t ub = q < kEscQ ? q + 1u : kEscQ;
-    if (pos + ub > nbits) { bad = true; return 0; }
-    skip(ub);
-    if (q == kEscQ) return take_wide(kb);
-    return ((uint64_t)q << r) | take_wide(r);
-  };
-  // pass 1: sum of this lane's deltas
-  uint64_t sum = 0;
-  if (active && !bad) {
-    seek(start);
-    for (uint32_t i = k0; i < k1 && !bad; i++) sum += next(i);
-    if (pos != stop) bad = true;
-  }
-  // exclusive prefix of the lane sums
-  uint64_t inc = sum;
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint64_t o = __shfl_up(inc, d, kWave);
-    if ((int)lane >= d) inc += o;
-  }
-  const bool any_bad = __ballot(bad) != 0;
-  if (any_bad) {
-    if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
-    return;
-  }
-  // pass 2: keys and coordinates
-  if (!active) return;
-  uint64_t k = inc - sum;
-  seek(start);
-  for (uint32_t i = k0; i < k1; i++) {
-    k += next(i);
-    const uint32_t px = compact3(k >> 2), py = compact3(k >> 1), pz = compact3(k);
-    ox[base + i] = (float)fma((double)(int32_t)px, step[0], (double)mn[0]);
-    oy[base + i] = (float)fma((double)(int32_t)py, step[1], (double)mn[1]);
-    oz[base + i] = (float)fma((double)(int32_t)pz, step[2], (double)mn[2]);
-  }
+  if (in_lds) run(std::true_type{}); else run(std::false_type{});
 }
 
 // Container (96-byte header): "SZMD" u16 1 u8 mode u8 nf u64 n u32 seg
