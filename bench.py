@@ -139,13 +139,6 @@ def _gbps(nbytes, ms):
     return round(nbytes / (ms * 1e-3) / 1e9, 2)
 
 
-def rebase(w):
-    """A slice of a long random walk restarted at zero and wrapped into
-    [0, 256), as a fresh walk of that length would be."""
-    import torch
-    return torch.remainder(w - w[0], 256.0).contiguous()
-
-
 def config1_steady(dev, walk, reps):
     """256 distinct random-walk fields of 2^20 values (1 GiB), LV, one
     graph-captured batched compression and one graph-captured batched
@@ -153,8 +146,9 @@ def config1_steady(dev, walk, reps):
     import torch
 
     from paper_1711_03888_amd import sznb
+    from paper_1711_03888_amd import datagen
     n, nf = 1 << 20, 256
-    fields = [rebase(walk[i * n:(i + 1) * n]) for i in range(nf)]
+    fields = [torch.from_numpy(f).to(dev) for f in datagen.steady_fields(walk, n, nf)]
     mode = sznb.PRED_LV | sznb.EB_REL
     plan = sznb.CompressPlan(fields, 1e-4, mode)
     side = torch.cuda.Stream()
@@ -218,19 +212,13 @@ def batched_512(dev, walk, cosmo, reps):
     {1e-3, 1e-4, 1e-5}): even fields are slices of a long random walk, odd
     fields slices of the cosmology snapshot; best-fit; autotuned block size
     and grid width; one graph-captured launch against per-field launches."""
-    import numpy as np
     import torch
 
     from paper_1711_03888_amd import datagen, sznb
-    specs = datagen.batch_spec()
-    rng = np.random.default_rng(4)
-    fields, ebs = [], []
-    for sp in specs:
-        n = sp["n"]
-        src = walk if sp["kind"] == "walk" else cosmo[sp["field"]]
-        off = int(rng.integers(0, (src.numel() - n) // 4 + 1)) * 4
-        fields.append(rebase(src[off:off + n]) if sp["kind"] == "walk" else src[off:off + n])
-        ebs.append(sp["eb_rel"])
+    specs, host = datagen.batch_from_sources(walk, cosmo)
+    fields = [torch.from_numpy(h).to(dev) for h in host]
+    ebs = [sp["eb_rel"] for sp in specs]
+    del host
     raw = 4.0 * sum(f.numel() for f in fields)
     policy = sznb.PRED_BESTFIT | sznb.EB_REL
     t0 = time.perf_counter()
@@ -409,9 +397,9 @@ def main():
     }
 
     if not args.no_batch:
-        walk = torch.from_numpy(datagen.random_walk(1 << 28, seed=7)).to(dev)
+        walk = datagen.random_walk(1 << 28, seed=7)
         out["config1_steady"] = config1_steady(dev, walk, max(3, args.steps))
-        out["batched_512"] = batched_512(dev, walk, fields, max(2, args.steps // 2))
+        out["batched_512"] = batched_512(dev, walk, snap, max(2, args.steps // 2))
         del walk
 
     if not args.no_learned and args.policy == "bestfit":

@@ -298,8 +298,12 @@ static void launch_E(bool quant, const Launch &P, hipStream_t s, int grid) {
   }
 }
 
+// workgroups per CU of the persistent per-block kernels (tunable)
+static int g_wg_per_cu = 8;
+
 // Workgroups of the quantization kernel: as many as stay resident together
-// (each takes a contiguous run of blocks), a multiple of the XCD count.
+// (each takes a contiguous run of blocks), at most the tunable width per CU,
+// a multiple of the XCD count.
 template <int E>
 static int quant_occupancy(bool learned, size_t smem) {
   int occ = 0;
@@ -317,13 +321,11 @@ static uint32_t quant_grid(int E, bool learned, const CLayout &L, int cus) {
     case 32: occ = quant_occupancy<32>(learned, smem); break;
     default: occ = quant_occupancy<64>(learned, smem); break;
   }
+  occ = std::min(occ, g_wg_per_cu);
   uint64_t g = std::min<uint64_t>({(uint64_t)cus * (uint64_t)occ, L.total_blocks, L.qmax});
   if (g > 8) g &= ~uint64_t(7);
   return (uint32_t)std::max<uint64_t>(g, 1);
 }
-
-// waves per CU used for the persistent per-block kernels (tunable)
-static int g_wg_per_cu = 8;
 
 static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params_only = false) {
   const CField *F = reinterpret_cast<const CField *>(P.ws + P.L.fields);

@@ -499,18 +499,22 @@ __device__ inline void block_features(const int32_t (&d)[E], const int32_t (&pv)
   if (k < kNFeat) s_feat[k] = kRound ? bf16_round(fv) : fv;
 }
 
-// Adds v (<= 64) to 16-bit counter idx16 of the LDS window; a counter that
-// wraps hands 65536 to its global histogram bin (and the carry it pushed
-// into its upper neighbour is taken back).
+// Adds v (<= 64) to 16-bit counter idx16 of the LDS window.  The add that
+// takes a counter from below 0x8000 to 0x8000 or more takes 0x8000 back out
+// and hands it to the counter's global histogram bin.  A block adds at most
+// S <= 0x4000 counts to one counter and ends at a barrier, so every counter
+// starts a block below 0x8000, crosses 0x8000 at most once in it, and never
+// exceeds 0xC000 - 1 + 64: it never carries into the neighbour sharing its
+// word, and no add reads a neighbour's transient value.
 __device__ inline void gadd(gptr<uint32_t> p, uint32_t v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void win_add(uint32_t *s_win, uint32_t idx16, uint32_t v, gptr<uint32_t> gbin) {
   const uint32_t sh = (idx16 & 1u) << 4;
-  const uint32_t old = atomicAdd(&s_win[idx16 >> 1], v << sh);
-  if (((old >> sh) & 0xffffu) + v > 0xffffu) {
-    if (!sh) atomicSub(&s_win[idx16 >> 1], 0x10000u);
-    gadd(gbin, 0x10000u);
+  const uint32_t c = (atomicAdd(&s_win[idx16 >> 1], v << sh) >> sh) & 0xffffu;
+  if (c < 0x8000u && c + v >= 0x8000u) {
+    atomicSub(&s_win[idx16 >> 1], 0x8000u << sh);
+    gadd(gbin, 0x8000u);
   }
 }
 

@@ -16,7 +16,10 @@ path receives the same bytes.
 * ``md_lattice``    -- three coordinate fields of an FCC lattice (a = 3.6)
   with N(0, 0.05) thermal displacements in lattice-index order, 5% of the
   256-atom blocks internally permuted.
-* ``batch_fields``  -- uneven fields drawn from the two generators above.
+* ``batch_spec`` / ``batch_field`` -- uneven fields drawn from the two
+  generators above; ``batch_from_sources`` cuts the same batch out of one
+  long random walk and one cosmology snapshot (much faster to generate).
+* ``steady_fields`` -- many equal random-walk fields cut from one long walk.
 """
 from __future__ import annotations
 
@@ -115,3 +118,33 @@ def batch_field(spec) -> np.ndarray:
     halos = max(1, int(round(20000 * n / float(1 << 26))))
     snap = cosmology(n, seed=spec["seed"], n_halos=halos)
     return snap[FIELD_NAMES[spec["field"]]]
+
+
+def rebased(w: np.ndarray) -> np.ndarray:
+    """A slice of a long random walk restarted at zero and wrapped into
+    [0, 256), as a fresh walk of that length would be."""
+    f = np.mod(w.astype(np.float64) - float(w[0]), 256.0).astype(np.float32)
+    f[f >= np.float32(256.0)] = np.float32(0.0)
+    return f
+
+
+def steady_fields(walk: np.ndarray, n: int = 1 << 20, nf: int = 256) -> list[np.ndarray]:
+    """nf distinct random-walk fields of n values: consecutive slices of one
+    long walk, each restarted at zero."""
+    return [rebased(walk[i * n:(i + 1) * n]) for i in range(nf)]
+
+
+def batch_from_sources(walk: np.ndarray, cosmo: dict, specs=None, seed: int = 4):
+    """The uneven batch of ``batch_spec`` cut from existing data: even fields
+    are slices of a long random walk (restarted at zero), odd fields slices
+    of the named field of a cosmology snapshot, at offsets drawn from
+    ``default_rng(seed)``.  Returns (specs, list of float32 arrays)."""
+    specs = batch_spec() if specs is None else specs
+    rng = np.random.default_rng(seed)
+    out = []
+    for sp in specs:
+        n = sp["n"]
+        src = walk if sp["kind"] == "walk" else cosmo[FIELD_NAMES[sp["field"]]]
+        off = int(rng.integers(0, (src.size - n) // 4 + 1)) * 4
+        out.append(rebased(src[off:off + n]) if sp["kind"] == "walk" else src[off:off + n])
+    return specs, out

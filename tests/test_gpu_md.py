@@ -92,3 +92,10 @@ def test_md_corrupt_container_is_rejected():
         sznb.md_decompress(bad, 3, n)
     outs = sznb.md_decompress(blob, 3, n)  # the good container still decodes
     assert outs[0].numel() == n
+
+
+@pytest.mark.parametrize("mode", [sznb.MD_SPEED, sznb.MD_TRADEOFF, sznb.MD_COMPRESSION])
+def test_md_full_size(mode):
+    # the benched FCC snapshot: 2^21 atoms, 128 segments of 16384
+    snap = datagen.md_lattice()
+    _run(list(snap.values()), 1e-4, mode, "full")

@@ -228,6 +228,34 @@ def test_histogram_counter_wraps():
     assert np.abs(y.astype(np.float64) - x).max() <= oracle.header(ref)["eb_abs"]
 
 
+def test_histogram_neighbour_counters_both_wrap():
+    # Residuals 0 and +1 in equal measure: codes 32768 and 32769 share one
+    # 32-bit word of the LDS window, and with one quantization workgroup per
+    # CU every workgroup visit covers 2^26 / 256 = 262144 values, so both
+    # counters of the word pass the 0x8000 hand-over point several times in
+    # the same visit.  Each block restarts at 0 (its first value is stored
+    # as the anchor), so the values stay small integers.
+    n, S = 1 << 26, 4096
+    print("neighbour wraps n=%d" % n, flush=True)
+    rng = np.random.default_rng(77)
+    steps = rng.integers(0, 2, size=(n // S, S), dtype=np.int32)
+    steps[:, 0] = 0
+    x = np.cumsum(steps, axis=1, dtype=np.int32).astype(np.float32).ravel()
+    del steps
+    mode = sznb.PRED_LV
+    ref = oracle.compress(x, 0.5, mode)
+    q = oracle.lattice(x, 0.5, eb_rel=False)
+    r = oracle.residuals(q, S, 0)
+    assert (r == 0).sum() > n // 3 and (r == 1).sum() > n // 3
+    sznb.set_workgroups_per_cu(1)
+    try:
+        got, y = _gpu_roundtrip(x, 0.5, mode)
+    finally:
+        sznb.set_workgroups_per_cu(8)
+    assert got == ref
+    assert np.abs(y.astype(np.float64) - x).max() <= 0.5
+
+
 def _unlimited_huffman_depth(w):
     """Depth of the deepest leaf of a Huffman tree without a length limit
     (heap merge of the two lightest nodes)."""

@@ -205,3 +205,88 @@ def test_adam_first_step():
     # bias-corrected first moments are g and g^2: a step of lr * g / (|g| + eps)
     assert np.allclose(w1, w0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+# ---- closed-form blocks for the features the ramp, zigzag and constant
+# blocks leave untouched (3, 9, 11, 12, 13).  S = 1024, sampled positions
+# j = 0, 4, ..., 1020 (m = 256, F(m) = 9).  Values of F are worked by hand:
+# F(v) = bit length + (the 8 bits after the leading one) / 256.
+
+def _feat(q):
+    return oracle.features(np.asarray(q, np.int32), 1024, 1 << 21)[0]
+
+
+def test_features_triangular_block():
+    # p_j = j(j-1)/2: Dp_j = j - 1 (j >= 1), D2p_j = 1 (j >= 2), D2p_1 = 0.
+    # Samples: D2p = 0 at j = 0, 1 at the 255 others.
+    j = np.arange(1024, dtype=np.int64)
+    f = _feat(j * (j - 1) // 2)
+    # feature 3: F(sum |D2p|) - F(m) = F(255) - 9; 255 = 0b11111111 -> 8 + 254/256
+    assert f[3] == np.float32(-2 / 256)
+    # feature 9: every sample has |D2p| <= 1 (a "< 1" would give 1/256)
+    assert f[9] == 1.0
+    assert f[7] == np.float32(1 / 256)
+    # feature 12: sum of bit lengths of |D2p| = 255 -> the same value as feature 3
+    assert f[12] == np.float32(-2 / 256)
+    # feature 11: sum over k = 1..255 of bitlen(4k - 1)
+    #   = 2*1 + 3*1 + 4*2 + 5*4 + 6*8 + 7*16 + 8*32 + 9*64 + 10*127 = 2295
+    #   2295 = 0b100011110111 -> 12 + 0b00011110/256 = 12 + 30/256
+    assert f[11] == np.float32(3 + 30 / 256)
+    assert f[5] == 1.0  # F(max |D2p|) = F(1) = 1
+
+
+def test_features_square_block():
+    # p_j = j^2: D2p_j = 2 for j >= 2; samples: 0 at j = 0, 2 at the others
+    j = np.arange(1024, dtype=np.int64)
+    f = _feat(j * j)
+    # feature 3: F(510) - 9; 510 = 0b111111110 -> 9 + 0b11111110/256 = 9 + 254/256
+    assert f[3] == np.float32(254 / 256)
+    # feature 9: only the first sample has |D2p| <= 1
+    assert f[9] == np.float32(1 / 256)
+    # feature 12: sum of bitlen(2) = 2 * 255 = 510, the same F
+    assert f[12] == np.float32(254 / 256)
+    assert f[5] == 2.0  # F(2)
+
+
+@pytest.mark.parametrize("amp,count", [(32768, 255), (32767, 0), (40000, 255)])
+def test_features_escape_count(amp, count):
+    # p alternates 0, amp: |Dp| = amp at every sample after the first
+    f = _feat(amp * (np.arange(1024) % 2))
+    assert f[13] == np.float32(count / 256)
+    assert f[8] == np.float32(1 / 256)
+
+
+# ---- training arithmetic: known values
+
+def test_loss_known_values():
+    w = np.zeros(mlp.NPARAM)
+    x = np.random.default_rng(1).normal(0, 1, (7, 16))
+    # zero weights: equal logits, the loss of each row is ln 3 (mean, not sum)
+    assert abs(mlp.loss(w, x, np.array([0, 1, 2, 0, 1, 2, 2])) - np.log(3.0)) < 1e-15
+    # a logit margin of 50 through the last bias: the labelled class costs
+    # ln(1 + 2 e^-50) ~ 3.9e-22, another class 50 + ln(1 + ... ) ~ 50
+    p = mlp.unpack(w)
+    p["b3"][:] = [50.0, 0.0, 0.0]
+    w = mlp.pack(p)
+    assert mlp.loss(w, x[:1], np.array([0])) < 1e-20
+    assert abs(mlp.loss(w, x[:1], np.array([1])) - 50.0) < 1e-12
+    # mixed labels average the two: (ln(e^50 + 2) - 50 + ln(e^50 + 2)) / 2
+    lse = 50.0 + np.log1p(2 * np.exp(-50.0))
+    assert abs(mlp.loss(w, x[:2], np.array([0, 2])) - (lse - 50.0 + lse) / 2) < 1e-12
+
+
+def test_adam_constant_gradient_many_steps():
+    # with a constant gradient the bias-corrected moments are exactly g and
+    # g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each
+    # step moves by lr g / (|g| + eps); a correction by b instead of b^t
+    # fails from t = 2 on
+    g = np.array([0.5, -2.0, 1e-3, 3.0])
+    w = np.zeros(4)
+    m = np.zeros(4)
+    v = np.zeros(4)
+    for t in range(1, 11):
+        w_prev = w
+        w, m, v = mlp.adam(w, m, v, g, t, 0.01)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-14, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(w - w_prev, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0), t
