@@ -41,7 +41,7 @@ MUTATIONS = [
     ("LOG table truncated", "sznb_oracle.c",
      "floor(65536.0 * log2((double)m) + 0.5)", "floor(65536.0 * log2((double)m))"),
     ("residual class boundary", "sznb_oracle.c",
-     "if (z < 4) { *cls = (int)z; *extra = 0; return; }", "if (z < 2) { *cls = (int)z; *extra = 0; return; }"),
+     "if (z < 4) { *cls = (int)z; *extra = 0; return; }", "if (z < 8) { *cls = (int)z; *extra = 0; return; }"),
     ("escape without extra bits", "sznb_oracle.c",
      "{ *cls = 32; *extra = 32; return; }", "{ *cls = 32; *extra = 0; return; }"),
     ("selection ties to the highest", "sznb_oracle.c",
@@ -49,7 +49,7 @@ MUTATIONS = [
     ("Huffman ties take the merged node", "sznb_oracle.c",
      "else take_leaf = L[lp].w <= iw[ip];", "else take_leaf = L[lp].w < iw[ip];"),
     ("halving rounds down", "sznb_oracle.c",
-     "w[s] = (w[s] + 1) >> 1;", "w[s] = (w[s] >> 1) | 1;"),
+     "w[s] = (w[s] + 1) >> 1;", "w[s] = w[s] >> 1;"),
     ("canonical code without shift", "sznb_oracle.c",
      "if (i > 0) c = (c + 1) << (len[order[i]] - len[order[i - 1]]);", "if (i > 0) c = (c + 1);"),
     ("bits packed LSB first", "sznb_oracle.c",
@@ -68,6 +68,10 @@ MUTATIONS = [
     ("hidden outputs not rounded", "sznb_oracle.c",
      "h2[j] = bf16_round(acc > 0.0f ? acc : 0.0f);", "h2[j] = acc > 0.0f ? acc : 0.0f;"),
     ("fallback on equal margin", "sznb_oracle.c", "if (!(margin >= tau)) {", "if (!(margin > tau)) {"),
+    ("decoder adds the residual with the wrong sign", "sznb_oracle.c",
+     "int64_t d0 = pred + r[j];", "int64_t d0 = pred - r[j];"),
+    ("decoder skips escapes", "sznb_oracle.c",
+     "r[j] = (int32_t)get_u32(s, base + 4 * (cwn + esc));", "r[j] = 0;"),
     ("loss summed", "mlp.py",
      "return float(np.mean(lse - z3[np.arange(len(y)), y]))", "return float(np.sum(lse - z3[np.arange(len(y)), y]))"),
     ("loss and gradient summed", "mlp.py", "dz3 /= B\n", "dz3 /= 1\n"),

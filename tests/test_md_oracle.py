@@ -4,6 +4,10 @@ Each pin checks the oracle against something other than itself: bit strings
 built character by character for the R-index, a literal 3-bit-digit LSD radix
 sort for PRX (Sec. 5.2), brute-force Rice parameter search, a hand-worked
 Rice example, lossless key round trips and the error bound of every mode.
+
+`tests/oracle_mutations.py` plants one plausible mistake at a time in a copy
+of the oracle (a dropped term, a wrong sign, index or tie rule) and checks
+that one of these pins fails for each.
 """
 import numpy as np
 import pytest
@@ -118,6 +122,20 @@ def test_cpc_escape_round_trip():
     assert r == 0
     # first key + parameter + three 1-deltas + escape + 1-delta + escape
     assert nbits == 45 + 6 + 3 * 2 + (32 + 45) + 2 + (32 + 45)
+    assert md.cpc_decode_segment(words, keys.size, 45).tolist() == keys.tolist()
+
+
+@pytest.mark.parametrize("nzero,r", [(58, 1), (59, 0)])
+def test_rice_escape_against_stop_bits(nzero, r):
+    # nzero zero deltas and one delta of 33 in 45-bit keys.  r = 0: the 33
+    # escapes (32 ones + 45 raw bits) and each zero costs its stop bit:
+    # nzero + 77.  r = 1: 33 -> quotient 16, 16 + 1 + 1 = 18 bits, each zero
+    # 2 bits: 2 nzero + 18.  58 zeros: 135 vs 134 -> r = 1; 59 zeros: 136 vs
+    # 136, a tie -> the smaller r = 0.
+    keys = np.concatenate([np.zeros(nzero + 1, np.uint64), np.uint64([33])])
+    assert md.rice_parameter(np.diff(keys), 45) == r
+    words, nbits = md.cpc_encode_segment(keys, 45)
+    assert nbits == 45 + 6 + (nzero + 77 if r == 0 else 2 * nzero + 18)
     assert md.cpc_decode_segment(words, keys.size, 45).tolist() == keys.tolist()
 
 

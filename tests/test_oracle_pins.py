@@ -7,6 +7,10 @@ max error equal to the bound, Sec. 6), Huffman optimality against an
 independent heap construction, the canonical-code worked example of RFC 1951
 Sec. 3.2.2, the exact log table, closed forms of the predictors on
 polynomial sequences, and an independent bit-level parse of the stream.
+
+`tests/oracle_mutations.py` plants one plausible mistake at a time in a copy
+of the oracle (a dropped term, a wrong sign, index or tie rule) and checks
+that one of these pins fails for each.
 """
 import heapq
 import math
@@ -390,3 +394,61 @@ def test_metrics_definitions():
 def test_walk_generator_shape():
     x = datagen.random_walk(1 << 16)
     assert x.dtype == np.float32 and x.min() >= 0 and x.max() < 256
+
+
+def test_reconstruction_rounds_once_before_float32():
+    # x~ = fl32(fma(p, step, mn)): the product is not rounded on its own.
+    # p = 257, step = k 2^-41 (k < 2^53), mn = -2^20: p step + mn is exactly
+    # 1 + 2^-24 + 32 2^-41, just above the float32 midpoint between 1 and
+    # 1 + 2^-23, so it rounds up; rounding p step to float64 first drops the
+    # 32 2^-41 (below half an ulp of 2^20) and lands on the midpoint, which
+    # rounds to even (1.0).
+    p, k = 257, (2 ** 61 + 2 ** 41 + 2 ** 17 + 32) // 257
+    assert k * 257 == 2 ** 61 + 2 ** 41 + 2 ** 17 + 32 and k < 2 ** 53
+    step, mn = k * 2.0 ** -41, -2.0 ** 20
+    exact = F(p) * F(step) + F(mn)
+    assert exact == 1 + F(1, 2 ** 24) + F(32, 2 ** 41)
+    assert oracle.reconstruct(p, step, mn) == 1 + 2.0 ** -23
+    assert np.float32(p * step + mn) == 1.0  # the two-rounding result differs
+
+
+def test_huffman_tie_takes_the_leaf():
+    # weights 1 1 2 2: after merging the two 1s the next pick ties a leaf (2)
+    # with the merged node (2).  Taking the leaves first pairs the two 2s:
+    # every length 2.  Taking the merged node first would give 3 3 2 1 (the
+    # same total cost, 12, so only the tie rule separates them).
+    f = np.zeros(65536, np.uint64)
+    f[[10, 11, 12, 13]] = [1, 1, 2, 2]
+    ln = oracle.huffman_lengths(f)
+    assert ln[[10, 11, 12, 13]].tolist() == [2, 2, 2, 2]
+
+
+def _heap_depth(w):
+    h = [(int(v), i, 0) for i, v in enumerate(w)]
+    heapq.heapify(h)
+    nxt = len(h)
+    while len(h) > 1:
+        a, b = heapq.heappop(h), heapq.heappop(h)
+        heapq.heappush(h, (a[0] + b[0], nxt, max(a[2], b[2]) + 1))
+        nxt += 1
+    return h[0][2]
+
+
+def test_huffman_length_limit_halves_with_rounding_up():
+    # Fibonacci-like weights whose natural depth exceeds 24: the code must be
+    # an optimal (heap-Huffman) code of the weights ceil(w / 2^h), h the
+    # fewest halvings whose optimal depth fits in 24 bits.
+    fib = [20, 21]
+    while len(fib) < 34:
+        fib.append(fib[-1] + fib[-2] + (len(fib) % 3 == 0))
+    w = np.array(fib, np.int64)
+    h = 0
+    while _heap_depth(-(-w // (1 << h))) > 24:
+        h += 1
+    assert h == 3
+    wh = -(-w // (1 << h))
+    f = np.zeros(65536, np.uint64)
+    f[500:500 + w.size] = w
+    ln = oracle.huffman_lengths(f)[500:500 + w.size].astype(np.int64)
+    assert ln.max() <= 24
+    assert int(np.sum(wh * ln)) == _heap_huffman_cost([int(v) for v in wh])

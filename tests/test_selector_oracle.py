@@ -5,6 +5,10 @@ Features are pinned by blocks whose statistics are known in closed form and
 by a vectorised numpy computation; inference by an exact rational emulation
 of each fused multiply-add with torch's own bfloat16 rounding; gradients by
 central finite differences; Adam by its first-step closed form.
+
+`tests/oracle_mutations.py` plants one plausible mistake at a time in a copy
+of the oracle (a dropped term, a wrong sign, index or tie rule) and checks
+that one of these pins fails for each.
 """
 from fractions import Fraction
 
@@ -290,3 +294,18 @@ def test_adam_constant_gradient_many_steps():
         assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-14, atol=0)
         assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
         assert np.allclose(w - w_prev, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=0), t
+
+
+def test_fallback_only_below_tau():
+    # all weights 0 and output biases (1, 0, 0): every block's logits are
+    # exactly (1, 0, 0), margin 1.  A margin equal to tau is trusted; one
+    # just below tau falls back to the exhaustive trial.
+    p = mlp.unpack(np.zeros(mlp.NPARAM))
+    p["b3"][:] = [1.0, 0.0, 0.0]
+    w = mlp.pack(p).astype(np.float32)
+    j = np.arange(3 * 1024, dtype=np.int64)
+    q = (5 * j * j % 7919).astype(np.int32)
+    pred, fb = oracle.select_learned(q, 1024, 1 << 20, w, 1.0)
+    assert not fb.any() and (pred == 0).all()
+    pred, fb = oracle.select_learned(q, 1024, 1 << 20, w, float(np.nextafter(np.float32(1), np.float32(2))))
+    assert fb.all() and np.array_equal(pred, oracle.select(q, 1024)[0])
