@@ -99,6 +99,19 @@ uint64_t sznb_decompress_workspace_bytes(int nf, const uint64_t *h_n);
 int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n,
                     void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code between allocations
+ * of a serving loop, harnesses that forbid hipMalloc): sznb_decompress
+ * without a workspace argument.  The library keeps a fixed 4 MiB workspace
+ * per GPU in device memory for the life of the process and never allocates
+ * in this call; fields of more than SZNB_NOALLOC_MAX_N values are refused
+ * with SZNB_ENOSPC.  Every call on one GPU shares that GPU's workspace:
+ * calls that overlap on one GPU (other host threads, other streams) race.
+ * The call waits for the stream (header read-back, then the decode) and
+ * returns the stream's status (SZNB_ECORRUPT for a corrupt stream). */
+#define SZNB_NOALLOC_MAX_N ((uint64_t)1 << 28)
+int sznb_decompress_noalloc(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n,
+                            hipStream_t stream);
+
 /* Decompress nf streams in one batched launch sequence. */
 int sznb_decompress_batch(int nf, const void *const *h_streams, const uint64_t *h_lens,
                           float *const *h_outs, const uint64_t *h_n,

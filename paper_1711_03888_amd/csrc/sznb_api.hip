@@ -107,12 +107,20 @@ static_assert(sizeof(DState) <= kStateStride, "DState too large");
 
 __device__ uint32_t g_logt[16385];
 
+// Workspace of the allocation-free decompression entry point: a fixed array
+// in device memory, one copy per GPU for the life of the process.  Host code
+// reaches it only through the address hipGetSymbolAddress gives per device
+// (DevInfo::scratch), never through its name.
+constexpr uint64_t kScratchBytes = 4ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
 struct DevInfo {
   int ok = 0;
   int cus = 0;
   size_t lds_per_block = 0;
   float *sel = nullptr;   // learned selector parameters on this device
   float tau = 0.0f;
+  uint8_t *scratch = nullptr;  // this device's copy of `scratch`
 };
 static DevInfo g_dev[64];
 static std::mutex g_mu;
@@ -131,6 +139,8 @@ static int dev_init(DevInfo **out) {
     std::vector<uint32_t> t(16385, 0u);
     for (int m = 1; m <= 16384; m++) t[m] = (uint32_t)std::floor(65536.0 * std::log2((double)m) + 0.5);
     if (hipMemcpyToSymbol(HIP_SYMBOL(g_logt), t.data(), t.size() * sizeof(uint32_t)) != hipSuccess) return SZNB_EDEVICE;
+    if (hipGetSymbolAddress(reinterpret_cast<void **>(&d.scratch), HIP_SYMBOL(scratch)) != hipSuccess || !d.scratch)
+      return SZNB_EDEVICE;
     if (hipDeviceSynchronize() != hipSuccess) return SZNB_EDEVICE;
     d.ok = 1;
   }
@@ -1158,6 +1168,19 @@ int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uin
                     uint64_t ws_bytes, hipStream_t stream) {
   float *outs[1] = {d_out};
   return decompress_impl(1, &d_stream, &stream_len, outs, &n, d_ws, ws_bytes, stream);
+}
+
+int sznb_decompress_noalloc(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n,
+                            hipStream_t stream) {
+  DevInfo *dv = nullptr;
+  int rc = dev_init(&dv);
+  if (rc) return rc;
+  if (n > SZNB_NOALLOC_MAX_N || decompress_layout(1, &n).total > kScratchBytes) return SZNB_ENOSPC;
+  float *outs[1] = {d_out};
+  rc = decompress_impl(1, &d_stream, &stream_len, outs, &n, dv->scratch, kScratchBytes, stream);
+  if (rc) return rc;
+  int st = SZNB_OK;
+  return sznb_read_status(dv->scratch, 1, &st, stream);
 }
 
 int sznb_decompress_batch(int nf, const void *const *h_streams, const uint64_t *h_lens, float *const *h_outs,

@@ -56,6 +56,7 @@ def lib():
         L.sznb_decompress_workspace_bytes.restype = _u64
         L.sznb_decompress.argtypes = [_vp, _u64, _vp, _u64, _vp, _u64, _vp]
         L.sznb_decompress_batch.argtypes = [ctypes.c_int, _vp, _vp, _vp, _vp, _vp, _u64, _vp]
+        L.sznb_decompress_noalloc.argtypes = [_vp, _u64, _vp, _u64, _vp]
         L.sznb_read_status.argtypes = [_vp, ctypes.c_int, _vp, _vp]
         L.sznb_profile.argtypes = [ctypes.c_int]
         L.sznb_profile_summary.argtypes = [ctypes.c_int, _vp, _vp, _vp]
@@ -221,6 +222,18 @@ def decompress_batch_async(streams: Sequence[torch.Tensor], ns: Sequence[int], *
                                      ws.data_ptr(), ws.numel(), _stream(stream))
     _check(rc, "decompress")
     return outs, ws
+
+
+def decompress_noalloc(s: torch.Tensor, n: int, *, out=None, stream=None) -> torch.Tensor:
+    """sznb_decompress_noalloc: decompression into `out` with the library's
+    fixed per-GPU workspace (waits for the stream, raises on a bad status)."""
+    if s.dtype != torch.uint8 or not s.is_cuda or not s.is_contiguous():
+        raise ValueError("stream must be a contiguous uint8 CUDA tensor")
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=s.device)
+    _check(lib().sznb_decompress_noalloc(s.data_ptr(), s.numel(), out.data_ptr(), int(n), _stream(stream)),
+           "decompress_noalloc")
+    return out
 
 
 def decompress_batch(streams, ns=None, **kw):
