@@ -82,6 +82,16 @@ MUTATIONS = [
     ("R-index z bit highest", "md.py",
      "key |= bit << np.uint64(3 * j + (2 - c))", "key |= bit << np.uint64(3 * j + c)"),
     ("PRX ignores bits, not digits", "md.py", "sk = key >> np.uint64(3 * k)", "sk = key >> np.uint64(k)"),
+    ("six-field key keeps the low bits", "md.py",
+     "lattice(f, eb_rel).astype(np.uint64) >> np.uint64(max(0, w - D))",
+     "lattice(f, eb_rel).astype(np.uint64) & np.uint64((1 << D) - 1)"),
+    ("six-field key with the vz bit highest", "md.py",
+     "key |= bit << np.uint64(6 * j + (5 - c))", "key |= bit << np.uint64(6 * j + c)"),
+    ("velocity values coded without the minimum", "md.py", "    d = vals - mn\n", "    d = vals\n"),
+    ("velocity entry points ignore the segment header", "md.py",
+     "starts = vbits + 6 + np.concatenate", "starts = np.concatenate"),
+    ("segments of the default size only", "md.py",
+     "        perm = segment_order(key, k, seg, digit)", "        perm = segment_order(key, k, SEG, digit)"),
     ("Rice ties to the larger parameter", "md.py",
      "if best_cost is None or cost < best_cost:", "if best_cost is None or cost <= best_cost:"),
     ("Rice cost without the stop bit", "md.py",

@@ -175,6 +175,7 @@ def test_container_layout():
     fields = list(snap.values())
     blob, _ = md.compress_md(fields, 1e-3, md.COMPRESSION)
     magic, ver, mode, nf, n, seg, k, total, *offs = struct.unpack_from("<4sHBBQIIQ6Q", blob, 0)
+    assert struct.unpack_from("<I", blob, 80)[0] == md.KEY_COORD
     assert (magic, ver, mode, nf, n, seg, k, total) == (b"SZMD", 1, 2, 6, fields[0].size, md.SEG, 0, len(blob))
     assert offs[0] == md.MD_HDR and all(o % 8 == 0 for o in offs[:4]) and offs[4:] == [0, 0]
     assert blob[offs[0]:offs[0] + 4] == b"SZCP"
@@ -202,3 +203,104 @@ def test_cpc_entry_points_start_codes():
         else:
             d = (q << r) | (int(bits[p + 1:p + 1 + r], 2) if r else 0)
         assert d == int(keys[256 * c] - keys[256 * c - 1])
+
+
+# ---- velocity keys, six-field keys, segment sizes and CPC2000 velocities
+
+def test_mode_word():
+    assert md.parse_mode(md.TRADEOFF) == (md.TRADEOFF, 16384, 6, md.KEY_COORD)
+    assert md.parse_mode(md.COMPRESSION) == (md.COMPRESSION, 16384, 0, md.KEY_COORD)
+    m = md.mode(md.TRADEOFF, seg_log2=12, ignored=0, key=md.KEY_ALL)
+    assert md.parse_mode(m) == (md.TRADEOFF, 4096, 0, md.KEY_ALL)
+    for bad in (7, md.mode(md.TRADEOFF, seg_log2=9), 1 << 18):
+        with pytest.raises(ValueError):
+            md.parse_mode(bad)
+
+
+def test_rindex6_matches_bit_strings():
+    # each of the six lattice indices cut to its D leading bits, then
+    # for each bit j from the top: xx_j yy_j zz_j vx_j vy_j vz_j
+    snap = _small_md(velocities=True)
+    fields = list(snap.values())
+    key, D = md.rindex_keys6(fields, 1e-4)
+    widths = [int(oracle.params(f, 1e-4)["P"]).bit_length() for f in fields]
+    assert D == min(max(widths), 10) and min(widths) > 10  # the cut is exercised
+    ps = [oracle.lattice(f, 1e-4) for f in fields]
+    for i in range(0, key.size, 89):
+        bs = [format(int(p[i]), "0%db" % w)[:D].rjust(D, "0") for p, w in zip(ps, widths)]
+        s = "".join(b[j] for j in range(D) for b in bs)
+        assert int(s, 2) == int(key[i]), i
+
+
+def _lsd_radix(keys, k, ndigits, digit):
+    order = list(range(len(keys)))
+    for d in range(k, ndigits):
+        buckets = [[] for _ in range(1 << digit)]
+        for i in order:
+            buckets[(int(keys[i]) >> (digit * d)) & ((1 << digit) - 1)].append(i)
+        order = [i for b in buckets for i in b]
+    return order
+
+
+@pytest.mark.parametrize("seg,k,digit", [(1024, 0, 3), (4096, 2, 6), (2048, 3, 3)])
+def test_prx_segments_and_six_bit_digits(seg, k, digit):
+    rng = np.random.default_rng(17)
+    n = 2 * seg + 777
+    keys = rng.integers(0, 1 << 36, size=n).astype(np.uint64)
+    keys[:300] &= np.uint64(0xfff)
+    perm = md.segment_order(keys, k, seg, digit)
+    for s in range(0, n, seg):
+        want = [s + i for i in _lsd_radix(keys[s:s + seg], k, 36 // digit, digit)]
+        assert perm[s:s + seg].tolist() == want
+
+
+def test_cpv_hand_example():
+    # values 7 5 9 5 in 4-bit values: minimum 5, offsets 2 0 4 0; Rice costs
+    # r=0: 3+1+5+1 = 10, r=1: 3+2+4+2 = 11, r=2: 3+3+4+3 = 13 -> r = 0.
+    # Bits: 0101 | 000000 | 110 | 0 | 11110 | 0; value 0 starts at bit 10
+    words, nbits, ent = md.cpv_encode_segment(np.array([7, 5, 9, 5], np.uint64), 4)
+    bits = "0101" + "000000" + "110" + "0" + "11110" + "0"
+    assert nbits == len(bits) == 20
+    assert words.tolist() == [int(bits + "0" * 12, 2)]
+    assert ent.tolist() == [10]
+    assert md.cpv_decode_segment(words, 4, 4).tolist() == [7, 5, 9, 5]
+
+
+def test_cpv_escape_and_entries():
+    rng = np.random.default_rng(5)
+    vals = rng.integers(0, 3000, size=700).astype(np.uint64)
+    vals[[10, 400]] = [1 << 20, (1 << 21) - 1]  # far above the rest: escaped
+    words, nbits, ent = md.cpv_encode_segment(vals, 21)
+    assert md.cpv_decode_segment(words, vals.size, 21).tolist() == vals.tolist()
+    bits = "".join(format(int(w), "032b") for w in words)
+    r = int(bits[21:27], 2)
+    mn = int(vals.min())
+    for c, e in enumerate(ent.tolist()):  # an independent reader started at each entry point
+        p, q = e, 0
+        while q < md.CPC_ESC_Q and bits[p] == "1":
+            q += 1
+            p += 1
+        d = int(bits[p:p + 21], 2) if q == md.CPC_ESC_Q else (q << r) | (int(bits[p + 1:p + 1 + r], 2) if r else 0)
+        assert mn + d == int(vals[256 * c])
+
+
+@pytest.mark.parametrize("m", [md.CPC2000, md.mode(md.TRADEOFF, 12, 0, md.KEY_VEL),
+                               md.mode(md.TRADEOFF, 12, 0, md.KEY_ALL), md.mode(md.TRADEOFF, 10, 4),
+                               md.mode(md.COMPRESSION, 11)])
+def test_md_variants_error_bound(m):
+    snap = _small_md(cells=(16, 16, 20), velocities=True)
+    fields = list(snap.values())
+    blob, perm = md.compress_md(fields, 1e-4, m)
+    out = md.decompress_md(blob)
+    assert np.array_equal(np.sort(perm), np.arange(fields[0].size))
+    kind, seg, _, _ = md.parse_mode(m)
+    for s in range(0, perm.size, seg):
+        assert perm[s:s + seg].min() >= s and perm[s:s + seg].max() < s + seg
+    for f, y in zip(fields, out):
+        eb_abs = oracle.params(f, 1e-4)["eb_abs"]
+        assert np.abs(f[perm].astype(np.float64) - y.astype(np.float64)).max() <= eb_abs
+    if kind == md.CPC2000:  # velocities come back on their own lattice
+        for f, y in zip(fields[3:], out[3:]):
+            pr = oracle.params(f, 1e-4)
+            want = oracle.reconstruct_array(oracle.lattice(f[perm], 1e-4), pr["step"], pr["mn"])
+            assert np.array_equal(y.view(np.uint32), want.view(np.uint32))
