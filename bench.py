@@ -67,7 +67,7 @@ def md_modes(dev, eb, reps):
     out = torch.empty(sznb.md_bound(3, n), dtype=torch.uint8, device=dev)
     outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)]
     res = {}
-    for mode, name in ((0, "best_speed"), (1, "best_tradeoff"), (2, "best_compression")):
+    for mode, name in ((0, "best_speed"), (1, "best_tradeoff"), (2, "best_compression"), (3, "cpc2000")):
         blob, _ = sznb.md_compress(fields, eb, mode, ws=ws, out=out)
         sznb.md_decompress(blob, 3, n, ws=ws, outs=outs)
         torch.cuda.synchronize()

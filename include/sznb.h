@@ -225,22 +225,39 @@ int sznb_mlp_adam(float *d_params, float *d_m, float *d_v, const float *d_grad, 
 int sznb_mlp_infer(const float *d_params, const float *d_feat, uint64_t nb, float *d_logits,
                    uint8_t *d_choice, float *d_margin, hipStream_t stream);
 
-/* ---- molecular-dynamics snapshots: the paper's three modes (Sec. 5.2, Sec. 6)
- * md_mode 0 best_speed:       SZ-LV on every field in stored order;
- * md_mode 1 best_tradeoff:    particles reordered by a stable sort of their
- *                             R-index without its 6 least significant 3-bit
- *                             digits inside 16384-particle segments (Table 5),
- *                             then SZ-LV on every field;
- * md_mode 2 best_compression: full R-index sort; the sorted coordinate keys
- *                             coded CPC2000-style (Rice-coded deltas), the
- *                             velocities by SZ-LV in the same order.
+/* ---- molecular-dynamics snapshots: the paper's modes (Sec. 5.2, Sec. 6)
+ * and its R-index studies (Tables 4-6)
+ * md_mode, low byte (the kind):
+ *   0 best_speed:       SZ-LV on every field in stored order;
+ *   1 best_tradeoff:    particles reordered by a stable sort of their
+ *                       R-index without its k least significant digits
+ *                       inside fixed index segments (Table 5: segment 16384,
+ *                       k = 6), then SZ-LV on every field;
+ *   2 best_compression: full R-index sort; the sorted coordinate keys coded
+ *                       CPC2000-style (Rice-coded deltas), the velocities by
+ *                       SZ-LV in the same order;
+ *   3 CPC2000:          as 2, with the velocities' lattice integers coded by
+ *                       CPC2000's variable-length code (per segment the
+ *                       minimum, then Rice-coded offsets; Sec. 2, Sec. 5.2).
+ * Further bits (SZNB_MD_*): segment size 2^s, s in 10..14 (default 16384);
+ * k + 1 in bits 12-15 (default: 6 for kind 1, 0 otherwise); the key fields
+ * (Sec. 5.3, Table 6): coordinates (default), velocities, or all six fields
+ * (each cut to its 10 leading bits, one bit of each per 6-bit digit; kind 1
+ * only, with six fields).  Kind 0 takes none of them.
  * h_fields: 3 coordinate fields (x, y, z), optionally followed by 3 velocity
  * fields, each of n values (device pointers, 16-byte aligned).  eb_rel is the
  * value-range-relative bound of every field.  The particles come back from
- * sznb_md_decompress in the stored order of the stream (reordered for modes 1
- * and 2: no index is kept, every field is permuted the same way); the
- * permutation is written to d_perm_or_null when given.  Both calls wait for
- * the stream and return the first device status. */
+ * sznb_md_decompress in the stored order of the container (reordered for
+ * kinds 1-3: no index is kept, every field is permuted the same way); the
+ * permutation is written to d_perm_or_null when given.
+ * Both calls enqueue their work and return without waiting for the GPU; the
+ * container length is written to the device word *d_out_len and the first
+ * error of the call (keying, any sub-stream, the container) is read with
+ * sznb_read_status(d_ws, 1, ...). */
+#define SZNB_MD_SEG_LOG2(s) ((int)(s) << 8)
+#define SZNB_MD_IGNORED(k) ((int)((k) + 1) << 12)
+#define SZNB_MD_KEY_VEL (1 << 16)
+#define SZNB_MD_KEY_ALL (2 << 16)
 uint64_t sznb_md_workspace_bytes(int nf, uint64_t n);
 uint64_t sznb_md_bound(int nf, uint64_t n);
 int sznb_md_compress(int nf, const float *const *h_fields, uint64_t n, double eb_rel, int md_mode,

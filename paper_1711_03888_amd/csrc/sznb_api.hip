@@ -42,20 +42,26 @@ __global__ void mlp_grad(const float *, const float *, uint32_t, float *);
 __global__ void mlp_loss(const float *, uint32_t, float *);
 __global__ void mlp_adam(float *, float *, float *, const float *, uint32_t, float, float, float, float);
 __global__ void mlp_infer(const float *, const float *, uint64_t, float *, uint8_t *, float *);
-struct MdCtl;
-__global__ void md_bits(const FState *, const FState *, const FState *, MdCtl *, uint64_t);
-__global__ void md_keys(const float *, const float *, const float *, uint64_t, const FState *, const FState *,
-                        const FState *, const MdCtl *, uint64_t *, uint32_t *);
+__global__ void md_bits(MdStates, int, MdStates, int, MdCtl *, uint64_t, uint32_t, uint32_t, uint32_t, uint32_t);
+__global__ void md_keys(MdPtrs, MdStates, uint64_t, const MdCtl *, uint64_t *, uint32_t *);
 __global__ void md_sort(uint64_t *, uint32_t *, uint64_t *, uint32_t *, uint64_t, uint32_t, const MdCtl *);
 __global__ void md_gather(const float *, float *, const uint32_t *, uint64_t, const MdCtl *);
-__global__ void cpc_count(const uint64_t *, uint64_t, const MdCtl *, uint32_t *, uint32_t *);
-__global__ void cpc_offsets(const uint32_t *, uint32_t, uint64_t, MdCtl *, const FState *, const FState *,
-                            const FState *, uint8_t *, uint32_t *);
+__global__ void md_vals(const float *, const uint32_t *, const FState *, uint64_t, const MdCtl *, uint64_t *);
+__global__ void md_iota(uint32_t *, uint64_t);
+template <bool kOffset>
+__global__ void cpc_count(const uint64_t *, uint64_t, const MdCtl *, const uint32_t *, uint32_t *, uint32_t *,
+                          uint64_t *);
+template <bool kOffset>
+__global__ void cpc_offsets(const uint32_t *, uint32_t, uint64_t, const MdCtl *, MdStates, int, uint8_t *, uint32_t *,
+                            uint64_t *);
+template <bool kOffset>
 __global__ void cpc_pack(const uint64_t *, uint64_t, const MdCtl *, const uint32_t *, const uint32_t *,
-                         const uint32_t *, uint8_t *);
-__global__ void cpc_decode(const uint8_t *, uint64_t, uint64_t, float *, float *, float *, int *);
-__global__ void md_assemble(uint8_t *, uint64_t, uint64_t *, const uint8_t *const *, const uint64_t *, int, int, int,
-                            uint64_t, uint32_t, const MdCtl *, int *);
+                         const uint32_t *, const uint32_t *, const uint64_t *, uint8_t *);
+__global__ void cpc_decode(const uint8_t *, const MdCtl *, uint64_t, float *, float *, float *, int *);
+__global__ void cpv_decode(const uint8_t *, const MdCtl *, int, uint64_t, float *, int *);
+__global__ void md_assemble(uint8_t *, uint64_t, uint64_t *, MdSubs, int, int, uint64_t, const MdCtl *, int *);
+__global__ void md_parse(const uint8_t *, uint64_t, int, uint64_t, MdCtl *, DField *, int *);
+__global__ void md_status(MdStatus, int, int32_t *);
 
 constexpr uint64_t kStateStride = 256;
 
@@ -149,6 +155,64 @@ static int dev_init(DevInfo **out) {
 }
 
 static inline uint64_t al256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+// ------------------------------------------------------ descriptor uploads
+// Host-built descriptors reach the workspace through pinned staging slots:
+// a copy from pinned memory is queued and the call returns without waiting;
+// a slot is refilled only after the event recorded behind its last copy.
+// Uploads larger than a slot (or with staging unavailable or not wanted)
+// are copied from the caller's memory and waited for.
+struct Upload {
+  void *dst;
+  const void *src;
+  size_t bytes;
+};
+constexpr int kStageSlots = 16;
+constexpr size_t kStageSlotBytes = 1u << 20;
+struct Staging {
+  uint8_t *buf = nullptr;
+  bool failed = false;
+  hipEvent_t ev[kStageSlots] = {};
+  bool used[kStageSlots] = {};
+  int next = 0;
+};
+static Staging g_stage[64];
+
+static int upload(const std::vector<Upload> &ups, hipStream_t s, bool may_stage) {
+  size_t tot = 0;
+  for (const Upload &u : ups) tot += al256(u.bytes);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SZNB_EDEVICE;
+  if (may_stage && tot <= kStageSlotBytes) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    Staging &g = g_stage[dev];
+    if (!g.buf && !g.failed) {
+      bool ok = hipHostMalloc(reinterpret_cast<void **>(&g.buf), kStageSlots * kStageSlotBytes, hipHostMallocDefault) ==
+                hipSuccess;
+      for (int i = 0; ok && i < kStageSlots; i++)
+        ok = hipEventCreateWithFlags(&g.ev[i], hipEventDisableTiming) == hipSuccess;
+      if (!ok) g.failed = true;
+    }
+    if (g.buf && !g.failed) {
+      const int slot = g.next;
+      g.next = (g.next + 1) % kStageSlots;
+      if (g.used[slot] && hipEventSynchronize(g.ev[slot]) != hipSuccess) return SZNB_EDEVICE;
+      uint8_t *p = g.buf + (size_t)slot * kStageSlotBytes;
+      for (const Upload &u : ups) {
+        std::memcpy(p, u.src, u.bytes);
+        if (hipMemcpyAsync(u.dst, p, u.bytes, hipMemcpyHostToDevice, s) != hipSuccess) return SZNB_EDEVICE;
+        p += al256(u.bytes);
+      }
+      if (hipEventRecord(g.ev[slot], s) != hipSuccess) return SZNB_EDEVICE;
+      g.used[slot] = true;
+      return SZNB_OK;
+    }
+  }
+  for (const Upload &u : ups)
+    if (hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s) != hipSuccess) return SZNB_EDEVICE;
+  // pageable source buffers must stay valid until the copies are consumed
+  return hipStreamSynchronize(s) == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
+}
 
 static int block_log2_of(uint32_t mode) {
   uint32_t b = (mode >> 8) & 15u;
@@ -418,14 +482,11 @@ static int compress_prepare(int nf, const float *const *fields, const uint64_t *
   const uint32_t gq = quant_grid((int)((1u << s0) / kThreads), learned, L, dv->cus);
   std::vector<uint32_t> qmeta;
   quant_plan(L, nf, gq, qmeta);
-  if (hipMemcpyAsync(ws + L.qmeta, qmeta.data(), 4 * qmeta.size(), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return SZNB_EDEVICE;
-  if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(CField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
-    return SZNB_EDEVICE;
-  if (hipMemcpyAsync(ws + L.fb0, fb0.data(), 8ull * (nf + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
-    return SZNB_EDEVICE;
-  // pageable source buffers must stay valid until the copies are consumed
-  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+  rc = upload({{ws + L.qmeta, qmeta.data(), 4 * qmeta.size()},
+               {ws + L.fields, hf.data(), sizeof(CField) * nf},
+               {ws + L.fb0, fb0.data(), 8ull * (nf + 1)}},
+              stream, true);
+  if (rc) return rc;
   P.cus = dv->cus;
   P.learned = learned;
   P.gq = gq;
@@ -767,8 +828,13 @@ struct DLaunch {
 // LDS layout: most resident waves per CU under the LDS of a CU, with the
 // tables once per workgroup and one code region per wave (1 KiB stays free
 // for the kernel's static LDS and alignment).
+// With `assumed` (largest block size, largest codebook size) the headers are
+// not read back: the launch is laid out for those sizes, the descriptors'
+// stream pointers are left to a kernel (MD containers: md_parse) and the
+// call does not wait for the GPU.
 static int decompress_prepare(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
-                              const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, DLaunch &P) {
+                              const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, DLaunch &P,
+                              const uint32_t *assumed = nullptr) {
   if (nf <= 0 || !d_ws) return SZNB_EINVAL;
   DevInfo *dv;
   int rc = dev_init(&dv);
@@ -778,13 +844,15 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   std::vector<DField> hf(nf);
   for (int f = 0; f < nf; f++) {
-    if (!streams[f] || lens[f] < kHdr || (reinterpret_cast<uintptr_t>(streams[f]) & 7u)) return SZNB_EINVAL;
+    if (!assumed && (!streams[f] || lens[f] < kHdr || (reinterpret_cast<uintptr_t>(streams[f]) & 7u)))
+      return SZNB_EINVAL;
     if (n[f] && (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 15u))) return SZNB_EINVAL;
     if (n[f] >= SZNB_MAX_N) return SZNB_EINVAL;
     DField &d = hf[f];
     std::memset(&d, 0, sizeof d);
-    d.in = static_cast<const uint8_t *>(streams[f]);
-    d.in_len = lens[f];
+    d.in = assumed ? nullptr : static_cast<const uint8_t *>(streams[f]);
+    d.in_len = assumed ? 0 : lens[f];
+    d.skip = assumed ? 1u : 0u;
     d.out = outs[f];
     d.n = n[f];
     d.nblocks_max = (uint32_t)L.nbmax[f];
@@ -795,22 +863,31 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
     d.slow = reinterpret_cast<uint32_t *>(ws + L.slow[f]);
     d.syms = reinterpret_cast<uint16_t *>(ws + L.syms[f]);
   }
-  if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(DField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
-    return SZNB_EDEVICE;
-  const DField *D = reinterpret_cast<const DField *>(ws + L.fields);
-  SZNB_LAUNCH("d_heads", d_heads, dim3((nf + 255) / 256), dim3(256), 0, stream, D, nf,
-              reinterpret_cast<uint32_t *>(ws + L.heads));
-  std::vector<uint32_t> heads(4ull * nf);
-  if (hipMemcpyAsync(heads.data(), ws + L.heads, 16ull * nf, hipMemcpyDeviceToHost, stream) != hipSuccess)
-    return SZNB_EDEVICE;
-  if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
   uint32_t smax = 1024, nsym_max = 0;
-  for (int f = 0; f < nf; f++) {
-    const uint32_t S = heads[4 * f];
-    if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
-    for (int k = 0; k < 3; k++) {
-      const uint32_t ns = heads[4 * f + 1 + k];
-      if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
+  if (assumed) {
+    rc = upload({{ws + L.fields, hf.data(), sizeof(DField) * nf}}, stream, true);
+    if (rc) return rc;
+    smax = assumed[0];
+    nsym_max = assumed[1];
+  } else {
+    if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(DField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return SZNB_EDEVICE;
+    const DField *D = reinterpret_cast<const DField *>(ws + L.fields);
+    SZNB_LAUNCH("d_heads", d_heads, dim3((nf + 255) / 256), dim3(256), 0, stream, D, nf,
+                reinterpret_cast<uint32_t *>(ws + L.heads));
+    std::vector<uint32_t> heads(4ull * nf);
+    if (hipMemcpyAsync(heads.data(), ws + L.heads, 16ull * nf, hipMemcpyDeviceToHost, stream) != hipSuccess)
+      return SZNB_EDEVICE;
+    // the header read-back: the launch layout depends on the block and
+    // codebook sizes (the pageable descriptor copy is consumed by then)
+    if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+    for (int f = 0; f < nf; f++) {
+      const uint32_t S = heads[4 * f];
+      if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
+      for (int k = 0; k < 3; k++) {
+        const uint32_t ns = heads[4 * f + 1 + k];
+        if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
+      }
     }
   }
   // the multi-symbol table pays when every codebook is small (short codes,
@@ -897,42 +974,71 @@ static int dplan_create(int nf, const void *const *streams, const uint64_t *lens
 
 // ------------------------------------------------------------ MD modes
 
-constexpr uint32_t kMdSeg = 16384;
 constexpr uint32_t kMdPrx = 6;  // Table 5: six ignored 3-bit digits
 constexpr uint32_t kMdMode = SZNB_PRED_LV | SZNB_EB_REL;
 
-struct MdLayout {
-  uint64_t ctl, status, cws, hdr, keys0, keys1, idx0, idx1, perm, subs, sublen, subptr, segr, segb, segw, coord, bws,
-      total;
-  uint64_t cws_bytes, hdr_cap, sub_cap, coord_cap, bws_bytes, nseg, perm_stride;
+// A decoded MD mode word (include/sznb.h).
+struct MdMode {
+  int kind = 0;          // 0 best_speed, 1 reorder + SZ-LV, 2 best_compression, 3 CPC2000
+  uint32_t seg = kMdSegMax;
+  uint32_t k = 0;        // ignored digits
+  int keysrc = 0;        // 0 coordinates, 1 velocities, 2 all six fields
 };
+static int md_mode_of(int mode, int nf, MdMode &m) {
+  const uint32_t u = (uint32_t)mode;
+  m.kind = (int)(u & 255u);
+  const uint32_t sl = (u >> 8) & 15u, kf = (u >> 12) & 15u;
+  m.keysrc = (int)((u >> 16) & 3u);
+  if (mode < 0 || (u >> 18) || m.kind > 3 || m.keysrc > 2 || (sl && (sl < 10 || sl > 14))) return SZNB_EINVAL;
+  m.seg = 1u << (sl ? sl : 14);
+  m.k = kf ? kf - 1 : (m.kind == 1 ? kMdPrx : 0u);
+  if (m.kind == 0 && (sl || kf || m.keysrc)) return SZNB_EINVAL;
+  if (m.keysrc && (nf != 6 || m.kind > 1)) return SZNB_EINVAL;
+  if ((m.keysrc == 2 ? 6u : 3u) * m.k >= 64u) return SZNB_EINVAL;
+  return SZNB_OK;
+}
+
+// MD workspace.  The call's status word sits where sznb_read_status(d_ws, 1)
+// reads it.
+struct MdLayout {
+  uint64_t status, ctl, cstat, cws, hdr, keys0, keys1, idx0, idx1, perm, subs, sublen, segr, segb, segw, segm, coord,
+      bws, total;
+  uint64_t cws_bytes, hdr_cap, sub_cap, coord_cap, bws_bytes, nseg_max, perm_stride;
+};
+
+static uint64_t md_vel_cap(uint64_t n, uint64_t nseg) {  // worst case of a CPC velocity stream
+  return kCvHdr + align8(4 * nseg) + align8(4 * (n / kMdSub + nseg)) + 8 * n + 8 * nseg + 64;
+}
 
 static MdLayout md_layout(int nf, uint64_t n) {
   MdLayout L;
   uint64_t o = 0;
-  L.nseg = (n + kMdSeg - 1) / kMdSeg;
-  L.ctl = o; o = al256(o + 256);
-  L.status = o; o = al256(o + 64);
-  uint64_t n3[3] = {n, n, n};
-  uint32_t m3[3] = {kMdMode, kMdMode, kMdMode};
-  L.cws_bytes = compress_layout(3, n3, m3).total;
+  L.nseg_max = (n + 1023) / 1024;
+  L.status = al256(sizeof(GCtl));
+  o = L.status + kStateStride;
+  L.ctl = o; o = al256(o + sizeof(MdCtl));
+  L.cstat = o; o = al256(o + 64);
+  std::vector<uint64_t> n6(6, n);
+  std::vector<uint32_t> m6(6, kMdMode);
+  L.cws_bytes = compress_layout(6, n6.data(), m6.data()).total;
   L.cws = o; o = al256(o + L.cws_bytes);
   L.hdr_cap = compress_min_cap_impl(n, kMdMode);
-  L.hdr = o; o = al256(o + 3 * L.hdr_cap);
+  L.hdr = o; o = al256(o + 6 * L.hdr_cap);
   L.keys0 = o; o = al256(o + 8 * n);
   L.keys1 = o; o = al256(o + 8 * n);
   L.idx0 = o; o = al256(o + 4 * n);
   L.idx1 = o; o = al256(o + 4 * n);
   L.perm_stride = al256(4 * n);
   L.perm = o; o = al256(o + L.perm_stride * nf);
-  L.sub_cap = al256(compress_bound_impl(n, kMdMode));
+  L.sub_cap = std::max(al256(compress_bound_impl(n, kMdMode)), al256(md_vel_cap(n, L.nseg_max)));
   L.subs = o; o = al256(o + L.sub_cap * nf);
   L.sublen = o; o = al256(o + 8 * 6);
-  L.subptr = o; o = al256(o + 8 * 6);
-  L.segr = o; o = al256(o + 4 * L.nseg);
-  L.segb = o; o = al256(o + 4 * L.nseg);
-  L.segw = o; o = al256(o + 4 * L.nseg);
-  L.coord_cap = 104 + align8(4 * L.nseg) + align8(4 * (n / 256 + L.nseg)) + 12 * n + 64 + 8 * L.nseg;
+  L.segr = o; o = al256(o + 4 * L.nseg_max);
+  L.segb = o; o = al256(o + 4 * L.nseg_max);
+  L.segw = o; o = al256(o + 4 * L.nseg_max);
+  L.segm = o; o = al256(o + 8 * L.nseg_max);
+  L.coord_cap = kCpHdr + align8(4 * L.nseg_max) + align8(4 * (n / kMdSub + L.nseg_max)) + 12 * n + 64 +
+                8 * L.nseg_max;
   L.coord = o; o = al256(o + L.coord_cap);
   std::vector<uint64_t> nn(nf, n);
   std::vector<uint32_t> mm(nf, kMdMode);
@@ -942,10 +1048,14 @@ static MdLayout md_layout(int nf, uint64_t n) {
   return L;
 }
 
+// Enqueues the whole MD compression; returns without waiting.  The status
+// of the call (first error of the keying, of any sub-stream, of the
+// container) lands in the status word; the container length in *d_out_len.
 static int md_compress_impl(int nf, const float *const *fields, uint64_t n, double eb_rel, int md_mode, void *d_out,
                             uint64_t out_cap, uint64_t *d_out_len, uint32_t *d_perm, void *d_ws, uint64_t ws_bytes,
                             hipStream_t s) {
-  if ((nf != 3 && nf != 6) || md_mode < 0 || md_mode > 2 || n == 0 || n >= SZNB_MAX_N || !d_out || !d_ws)
+  MdMode M;
+  if ((nf != 3 && nf != 6) || md_mode_of(md_mode, nf, M) || n == 0 || n >= SZNB_MAX_N || !d_out || !d_ws)
     return SZNB_EINVAL;
   if (!(eb_rel > 0.0) || !std::isfinite(eb_rel)) return SZNB_EINVAL;
   for (int f = 0; f < nf; f++)
@@ -957,101 +1067,140 @@ static int md_compress_impl(int nf, const float *const *fields, uint64_t n, doub
   if (ws_bytes < L.total) return SZNB_ENOSPC;
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   MdCtl *ctl = reinterpret_cast<MdCtl *>(ws + L.ctl);
-  int *dstatus = reinterpret_cast<int *>(ws + L.status);
-  if (hipMemsetAsync(ws + L.ctl, 0, 256 + 64, s) != hipSuccess) return SZNB_EDEVICE;
-  const uint32_t k_ign = md_mode == 1 ? kMdPrx : 0u;
+  int *cstat = reinterpret_cast<int *>(ws + L.cstat);
+  if (hipMemsetAsync(ws + L.ctl, 0, L.cstat + 64 - L.ctl, s) != hipSuccess) return SZNB_EDEVICE;
   const int grid = dv->cus * 8;
-  // the SZ-LV inputs: the fields themselves, or their reordered copies
-  std::vector<const float *> szf;
-  const FState *cst[3] = {nullptr, nullptr, nullptr};
-  if (md_mode == 0) {
-    for (int f = 0; f < nf; f++) szf.push_back(fields[f]);
-  } else {
-    // coordinate lattices exactly as the compressor computes them
-    uint64_t n3[3] = {n, n, n};
-    double e3[3] = {eb_rel, eb_rel, eb_rel};
-    uint32_t m3[3] = {kMdMode, kMdMode, kMdMode};
-    void *ho[3];
-    uint64_t hc[3];
-    for (int c = 0; c < 3; c++) { ho[c] = ws + L.hdr + c * L.hdr_cap; hc[c] = L.hdr_cap; }
-    rc = compress_impl(3, fields, n3, e3, m3, ho, hc, nullptr, false, ws + L.cws, L.cws_bytes, s, true);
+  const unsigned nseg = (unsigned)((n + M.seg - 1) / M.seg);
+  uint32_t *i0 = reinterpret_cast<uint32_t *>(ws + L.idx0), *i1 = reinterpret_cast<uint32_t *>(ws + L.idx1);
+  uint64_t *k0 = reinterpret_cast<uint64_t *>(ws + L.keys0), *k1 = reinterpret_cast<uint64_t *>(ws + L.keys1);
+  // the fields whose range and bound the keys and CPC2000 values need,
+  // computed exactly as the compressor computes them
+  std::vector<int> pf;
+  if (M.kind >= 1) {
+    if (M.keysrc != 1) for (int c = 0; c < 3; c++) pf.push_back(c);
+    if (M.keysrc >= 1 || (M.kind == 3 && nf == 6)) for (int c = 3; c < 6; c++) pf.push_back(c);
+  }
+  const int np = (int)pf.size();
+  auto state_of = [&](int f) -> const FState * {
+    std::vector<uint64_t> nn(np, n);
+    std::vector<uint32_t> mm(np, kMdMode);
+    CLayout CL = compress_layout(np, nn.data(), mm.data());
+    for (int i = 0; i < np; i++)
+      if (pf[i] == f) return reinterpret_cast<const FState *>(ws + L.cws + CL.states + kStateStride * i);
+    return nullptr;
+  };
+  MdStates ks{}, vs{};
+  MdPtrs kf{};
+  int nk = 0, nv = 0;
+  if (np) {
+    std::vector<const float *> pp(np);
+    std::vector<uint64_t> nn(np, n);
+    std::vector<double> ee(np, eb_rel);
+    std::vector<uint32_t> mm(np, kMdMode);
+    std::vector<void *> ho(np);
+    std::vector<uint64_t> hc(np, L.hdr_cap);
+    for (int i = 0; i < np; i++) { pp[i] = fields[pf[i]]; ho[i] = ws + L.hdr + i * L.hdr_cap; }
+    rc = compress_impl(np, pp.data(), nn.data(), ee.data(), mm.data(), ho.data(), hc.data(), nullptr, false,
+                       ws + L.cws, L.cws_bytes, s, true);
     if (rc) return rc;
-    CLayout CL = compress_layout(3, n3, m3);
-    for (int c = 0; c < 3; c++) cst[c] = reinterpret_cast<const FState *>(ws + L.cws + CL.states + kStateStride * c);
-    uint64_t *k0 = reinterpret_cast<uint64_t *>(ws + L.keys0), *k1 = reinterpret_cast<uint64_t *>(ws + L.keys1);
-    uint32_t *i0 = reinterpret_cast<uint32_t *>(ws + L.idx0), *i1 = reinterpret_cast<uint32_t *>(ws + L.idx1);
-    SZNB_LAUNCH("md_bits", md_bits, dim3(1), dim3(64), 0, s, cst[0], cst[1], cst[2], ctl, n);
-    // a coordinate that cannot be keyed stops here, before any reordering
-    uint32_t hc4[4];
-    if (hipMemcpyAsync(hc4, ctl, 16, hipMemcpyDeviceToHost, s) != hipSuccess) return SZNB_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
-    if (hc4[3]) return (int)hc4[3];
-    SZNB_LAUNCH("md_keys", md_keys, dim3(grid), dim3(256), 0, s, fields[0], fields[1], fields[2], n, cst[0], cst[1],
-                cst[2], ctl, k0, i0);
-    SZNB_LAUNCH("md_sort", md_sort, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, i0, k1, i1, n, k_ign, ctl);
-    const int first = md_mode == 2 ? 3 : 0;
+    const int k0f = M.keysrc == 1 ? 3 : 0;
+    nk = M.keysrc == 2 ? 6 : 3;
+    for (int c = 0; c < nk; c++) { ks.s[c] = state_of(k0f + c); kf.f[c] = fields[k0f + c]; }
+    if (M.kind == 3)
+      for (int c = 3; c < nf; c++) vs.s[nv++] = state_of(c);
+  }
+  SZNB_LAUNCH("md_bits", md_bits, dim3(1), dim3(64), 0, s, ks, nk, vs, nv, ctl, n, M.seg, (uint32_t)M.kind,
+              (uint32_t)M.keysrc, M.k);
+  std::vector<const float *> szf;   // the SZ-LV inputs: the fields, or their reordered copies
+  if (M.kind == 0) {
+    for (int f = 0; f < nf; f++) szf.push_back(fields[f]);
+    if (d_perm) SZNB_LAUNCH("md_iota", md_iota, dim3(grid), dim3(256), 0, s, d_perm, n);
+  } else {
+    SZNB_LAUNCH("md_keys", md_keys, dim3(grid), dim3(256), 0, s, kf, ks, n, ctl, k0, i0);
+    SZNB_LAUNCH("md_sort", md_sort, dim3(nseg), dim3(1024), 0, s, k0, i0, k1, i1, n, M.k, ctl);
+    const int first = M.kind == 2 ? 3 : M.kind == 3 ? nf : 0;
     for (int f = first; f < nf; f++) {
-      float *pf = reinterpret_cast<float *>(ws + L.perm + L.perm_stride * f);
-      SZNB_LAUNCH("md_gather", md_gather, dim3(grid), dim3(256), 0, s, fields[f], pf, i0, n, ctl);
-      szf.push_back(pf);
+      float *pfp = reinterpret_cast<float *>(ws + L.perm + L.perm_stride * f);
+      SZNB_LAUNCH("md_gather", md_gather, dim3(grid), dim3(256), 0, s, fields[f], pfp, i0, n, ctl);
+      szf.push_back(pfp);
     }
-    if (md_mode == 2) {
-      uint32_t *sr = reinterpret_cast<uint32_t *>(ws + L.segr), *sbits = reinterpret_cast<uint32_t *>(ws + L.segb);
-      uint32_t *sw = reinterpret_cast<uint32_t *>(ws + L.segw);
+    uint32_t *sr = reinterpret_cast<uint32_t *>(ws + L.segr), *sbits = reinterpret_cast<uint32_t *>(ws + L.segb);
+    uint32_t *sw = reinterpret_cast<uint32_t *>(ws + L.segw);
+    uint64_t *sm = reinterpret_cast<uint64_t *>(ws + L.segm);
+    if (M.kind >= 2) {
       uint8_t *cs = ws + L.coord;
-      SZNB_LAUNCH("cpc_count", cpc_count, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, n, ctl, sr, sbits);
-      SZNB_LAUNCH("cpc_offsets", cpc_offsets, dim3(1), dim3(64), 0, s, sbits, (uint32_t)L.nseg, n, ctl, cst[0], cst[1],
-                  cst[2], cs, sw);
-      SZNB_LAUNCH("cpc_pack", cpc_pack, dim3((unsigned)L.nseg), dim3(1024), 0, s, k0, n, ctl, sr, sbits, sw, cs);
+      SZNB_LAUNCH("cpc_count", cpc_count<false>, dim3(nseg), dim3(1024), 0, s, k0, n, ctl, &ctl->keybits, sr, sbits,
+                  sm);
+      SZNB_LAUNCH("cpc_offsets", cpc_offsets<false>, dim3(1), dim3(64), 0, s, sbits, (uint32_t)L.nseg_max, n, ctl,
+                  ks, 0, cs, sw, &ctl->coord_bytes);
+      SZNB_LAUNCH("cpc_pack", cpc_pack<false>, dim3(nseg), dim3(1024), 0, s, k0, n, ctl, &ctl->keybits, sr, sbits,
+                  sw, sm, cs);
+    }
+    if (M.kind == 3) {
+      for (int j = 0; j < nv; j++) {
+        uint8_t *vsb = ws + L.subs + (uint64_t)j * L.sub_cap;
+        MdStates one{};
+        one.s[0] = vs.s[j];
+        SZNB_LAUNCH("md_vals", md_vals, dim3(grid), dim3(256), 0, s, fields[3 + j], i0, vs.s[j], n, ctl, k1);
+        SZNB_LAUNCH("cpc_count", cpc_count<true>, dim3(nseg), dim3(1024), 0, s, k1, n, ctl, &ctl->vbits[j], sr,
+                    sbits, sm);
+        SZNB_LAUNCH("cpc_offsets", cpc_offsets<true>, dim3(1), dim3(64), 0, s, sbits, (uint32_t)L.nseg_max, n, ctl,
+                    one, j, vsb, sw, &ctl->vel_bytes[j]);
+        SZNB_LAUNCH("cpc_pack", cpc_pack<true>, dim3(nseg), dim3(1024), 0, s, k1, n, ctl, &ctl->vbits[j], sr, sbits,
+                    sw, sm, vsb);
+      }
     }
     if (d_perm && hipMemcpyAsync(d_perm, i0, 4 * n, hipMemcpyDeviceToDevice, s) != hipSuccess) return SZNB_EDEVICE;
   }
-  if (md_mode == 0 && d_perm) {
-    // identity order
-    std::vector<uint32_t> id(n);
-    for (uint64_t i = 0; i < n; i++) id[i] = (uint32_t)i;
-    if (hipMemcpy(d_perm, id.data(), 4 * n, hipMemcpyHostToDevice) != hipSuccess) return SZNB_EDEVICE;
-  }
   // SZ-LV streams of the (reordered) fields
   const int nsz = (int)szf.size();
-  std::vector<const uint8_t *> subp;
-  if (md_mode == 2) subp.push_back(ws + L.coord);
+  const int szbase = M.kind == 3 ? nv : 0;  // CPC2000's velocity streams take the first sub-stream buffers
+  MdSubs subs{};
+  int nsub = 0;
+  if (M.kind >= 2) { subs.p[nsub] = ws + L.coord; subs.len[nsub] = &ctl->coord_bytes; nsub++; }
+  for (int j = 0; M.kind == 3 && j < nv; j++) {
+    subs.p[nsub] = ws + L.subs + (uint64_t)j * L.sub_cap;
+    subs.len[nsub] = &ctl->vel_bytes[j];
+    nsub++;
+  }
   uint64_t *sublen = reinterpret_cast<uint64_t *>(ws + L.sublen);
+  MdStatus ss{};
+  int nss = 0;
+  ss.s[nss++] = reinterpret_cast<const int32_t *>(&ctl->status);
   if (nsz) {
     std::vector<uint64_t> nn(nsz, n), caps(nsz, L.sub_cap);
     std::vector<double> ee(nsz, eb_rel);
     std::vector<uint32_t> mm(nsz, kMdMode);
     std::vector<void *> outs(nsz);
-    for (int i = 0; i < nsz; i++) outs[i] = ws + L.subs + (uint64_t)i * L.sub_cap;
-    rc = compress_impl(nsz, szf.data(), nn.data(), ee.data(), mm.data(), outs.data(), caps.data(),
-                       sublen + (md_mode == 2 ? 1 : 0), true, ws + L.bws, L.bws_bytes, s);
+    for (int i = 0; i < nsz; i++) outs[i] = ws + L.subs + (uint64_t)(szbase + i) * L.sub_cap;
+    rc = compress_impl(nsz, szf.data(), nn.data(), ee.data(), mm.data(), outs.data(), caps.data(), sublen, true,
+                       ws + L.bws, L.bws_bytes, s);
     if (rc) return rc;
-    for (int i = 0; i < nsz; i++) subp.push_back(static_cast<const uint8_t *>(outs[i]));
+    for (int i = 0; i < nsz; i++) {
+      subs.p[nsub] = static_cast<const uint8_t *>(outs[i]);
+      subs.len[nsub] = sublen + i;
+      nsub++;
+      ss.s[nss++] = reinterpret_cast<const int32_t *>(ws + L.bws + al256(sizeof(GCtl)) + kStateStride * i);
+    }
   }
-  const int nsub = (int)subp.size();
-  if (hipMemcpyAsync(ws + L.subptr, subp.data(), 8ull * nsub, hipMemcpyHostToDevice, s) != hipSuccess)
-    return SZNB_EDEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
   SZNB_LAUNCH("md_assemble", md_assemble, dim3(grid), dim3(256), 0, s, static_cast<uint8_t *>(d_out), out_cap,
-              d_out_len, reinterpret_cast<const uint8_t *const *>(ws + L.subptr), sublen, nsub, md_mode, nf, n, k_ign,
-              ctl, dstatus);
-  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
-  // statuses: every SZ stream, then the container (whose ENOSPC may only
-  // echo a failed sub-stream)
-  for (int i = 0; i < nsz; i++) {
-    int v = 0;
-    if (hipMemcpy(&v, ws + L.bws + al256(sizeof(GCtl)) + kStateStride * i, 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return SZNB_EDEVICE;
-    if (v) return v;
-  }
-  int st = 0;
-  if (hipMemcpy(&st, dstatus, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
-  return st;
+              d_out_len, subs, nsub, nf, n, ctl, cstat);
+  // statuses: the keying, every SZ stream, then the container (whose ENOSPC
+  // may only echo a failed sub-stream)
+  ss.s[nss++] = cstat;
+  SZNB_LAUNCH("md_status", md_status, dim3(1), dim3(64), 0, s, ss, nss, reinterpret_cast<int32_t *>(ws + L.status));
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
+// Enqueues the whole MD decompression; returns without waiting (status as
+// for compression).  The container header is read on the device: md_parse
+// points the SZ-LV decoder's descriptors and the CPC decoders at the
+// sub-streams, so the host needs nothing from the stream.
 static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_t n, float *const *outs, void *d_ws,
                               uint64_t ws_bytes, hipStream_t s) {
-  if ((nf != 3 && nf != 6) || !d_in || in_len < 96 || n == 0 || n >= SZNB_MAX_N || !d_ws) return SZNB_EINVAL;
+  if ((nf != 3 && nf != 6) || !d_in || (reinterpret_cast<uintptr_t>(d_in) & 7u) || in_len < kMdHdr || n == 0 ||
+      n >= SZNB_MAX_N || !d_ws)
+    return SZNB_EINVAL;
   for (int f = 0; f < nf; f++)
     if (!outs[f] || (reinterpret_cast<uintptr_t>(outs[f]) & 15u)) return SZNB_EINVAL;
   DevInfo *dv;
@@ -1059,57 +1208,33 @@ static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_
   if (rc) return rc;
   MdLayout L = md_layout(nf, n);
   if (ws_bytes < L.total) return SZNB_ENOSPC;
-  uint8_t h[96];
-  if (hipMemcpyAsync(h, d_in, 96, hipMemcpyDeviceToHost, s) != hipSuccess) return SZNB_EDEVICE;
-  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
-  uint32_t magic;
-  uint64_t hn, total, offs[6];
-  std::memcpy(&magic, h, 4);
-  const int md_mode = h[6], hnf = h[7];
-  std::memcpy(&hn, h + 8, 8);
-  std::memcpy(&total, h + 24, 8);
-  std::memcpy(offs, h + 32, 48);
-  if (magic != 0x444D5A53u || h[4] != 1 || md_mode > 2 || hnf != nf || hn != n || total > in_len) return SZNB_ECORRUPT;
-  const int nsub = md_mode == 2 ? nf - 2 : nf;
-  uint64_t ends[6];
-  for (int i = 0; i < nsub; i++) {
-    ends[i] = i + 1 < nsub ? offs[i + 1] : total;
-    if (offs[i] < 96 || ends[i] < offs[i] || ends[i] > total || (offs[i] & 7u)) return SZNB_ECORRUPT;
-  }
   uint8_t *ws = static_cast<uint8_t *>(d_ws);
   const uint8_t *in = static_cast<const uint8_t *>(d_in);
-  int *dstatus = reinterpret_cast<int *>(ws + L.status);
-  if (hipMemsetAsync(dstatus, 0, 4, s) != hipSuccess) return SZNB_EDEVICE;
-  int first = 0;
-  if (md_mode == 2) {
-    SZNB_LAUNCH("cpc_decode", cpc_decode, dim3((unsigned)L.nseg), dim3(kWave), 0, s, in + offs[0],
-                ends[0] - offs[0], n, outs[0], outs[1], outs[2], dstatus);
-    first = 1;
-  }
-  const int nsz = nsub - first;
-  if (nsz) {
-    std::vector<const void *> st(nsz);
-    std::vector<uint64_t> ln(nsz), nn(nsz, n);
-    std::vector<float *> oo(nsz);
-    for (int i = 0; i < nsz; i++) {
-      st[i] = in + offs[first + i];
-      ln[i] = ends[first + i] - offs[first + i];
-      oo[i] = outs[md_mode == 2 ? 3 + i : i];
-    }
-    rc = decompress_impl(nsz, st.data(), ln.data(), oo.data(), nn.data(), ws + L.bws, L.bws_bytes, s);
-    if (rc) return rc;
-  }
-  if (hipStreamSynchronize(s) != hipSuccess) return SZNB_EDEVICE;
-  int stv = 0;
-  if (hipMemcpy(&stv, dstatus, 4, hipMemcpyDeviceToHost) != hipSuccess) return SZNB_EDEVICE;
-  if (stv) return stv;
-  for (int i = 0; i < nsz; i++) {
-    int v = 0;
-    if (hipMemcpy(&v, ws + L.bws + al256(sizeof(GCtl)) + kStateStride * i, 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return SZNB_EDEVICE;
-    if (v) return v;
-  }
-  return SZNB_OK;
+  MdCtl *ctl = reinterpret_cast<MdCtl *>(ws + L.ctl);
+  int *cstat = reinterpret_cast<int *>(ws + L.cstat);
+  if (hipMemsetAsync(ws + L.ctl, 0, L.cstat + 64 - L.ctl, s) != hipSuccess) return SZNB_EDEVICE;
+  // SZ-LV sub-streams are 4096-value blocks; codebooks up to 8192 symbols
+  // keep their symbols in LDS
+  const uint32_t assumed[2] = {4096u, 8192u};
+  std::vector<uint64_t> nn(nf, n);
+  DLaunch P;
+  rc = decompress_prepare(nf, nullptr, nullptr, outs, nn.data(), ws + L.bws, L.bws_bytes, s, P, assumed);
+  if (rc) return rc;
+  DField *D = reinterpret_cast<DField *>(P.ws + P.L.fields);
+  SZNB_LAUNCH("md_parse", md_parse, dim3(1), dim3(64), 0, s, in, in_len, nf, n, ctl, D, cstat);
+  rc = decompress_run(P, s);
+  if (rc) return rc;
+  const unsigned gmax = (unsigned)L.nseg_max;  // the smallest segment size's count: extra workgroups return
+  SZNB_LAUNCH("cpc_decode", cpc_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, n, outs[0], outs[1], outs[2], cstat);
+  for (int j = 0; j + 3 < nf; j++)
+    SZNB_LAUNCH("cpv_decode", cpv_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, j, n, outs[3 + j], cstat);
+  MdStatus ss{};
+  int nss = 0;
+  ss.s[nss++] = cstat;
+  for (int f = 0; f < nf; f++)
+    ss.s[nss++] = reinterpret_cast<const int32_t *>(P.ws + P.L.states + kStateStride * f);
+  SZNB_LAUNCH("md_status", md_status, dim3(1), dim3(64), 0, s, ss, nss, reinterpret_cast<int32_t *>(ws + L.status));
+  return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 
 }  // namespace sznb
@@ -1289,7 +1414,8 @@ int sznb_mlp_infer(const float *d_params, const float *d_feat, uint64_t nb, floa
 uint64_t sznb_md_workspace_bytes(int nf, uint64_t n) { return md_layout(nf, n).total; }
 
 uint64_t sznb_md_bound(int nf, uint64_t n) {
-  return 96 + (uint64_t)nf * align8(compress_bound_impl(n, kMdMode)) + align8(md_layout(nf, n).coord_cap);
+  const MdLayout L = md_layout(nf, n);
+  return kMdHdr + (uint64_t)nf * L.sub_cap + align8(L.coord_cap);
 }
 
 int sznb_md_compress(int nf, const float *const *h_fields, uint64_t n, double eb_rel, int md_mode, void *d_out,

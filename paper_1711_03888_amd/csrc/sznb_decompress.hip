@@ -53,6 +53,15 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
   __shared__ uint32_t s_tot[kPrepThreads / kWave][4];
   // the header, read by 32 threads at once and parsed from LDS
   __shared__ uint32_t s_hdr[kHdr / 4];
+  if (df.skip) {  // an unused descriptor of an MD container: no stream, no work
+    if (t == 0) {
+      st->status = 0;
+      st->is_const = 0;
+      st->nblocks = 0;
+      for (int k = 0; k < 3; k++) { st->nsym[k] = 0; st->grp_count[k] = 0; st->grp_start[k] = 0; }
+    }
+    return;
+  }
   if (t < kHdr / 4) s_hdr[t] = df.in_len >= (uint64_t)kHdr ? rd32(G(in), 4ull * t) : 0u;
   __syncthreads();
   if (t == 0) {

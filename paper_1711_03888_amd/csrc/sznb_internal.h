@@ -180,7 +180,7 @@ struct alignas(16) DField {
   float *out;
   uint64_t n;             // expected field size
   uint32_t nblocks_max;
-  uint32_t pad;
+  uint32_t skip;          // set on the device: this descriptor decodes nothing
   DState *st;
   uint32_t *boff;         // payload word offset of every block
   uint32_t *order;        // block ids grouped by predictor
@@ -193,6 +193,40 @@ constexpr int kSlowWords = 128;
 // decode-table entry: sym | len << 16; flags
 constexpr uint32_t kLutLong = 1u << 22;
 constexpr uint32_t kLutInvalid = 1u << 23;
+
+// ------------------------------------------------------------ MD modes
+
+constexpr uint32_t kMdSegMax = 16384;  // largest reorder / CPC segment
+constexpr uint32_t kMdSub = 256;       // values per CPC decoder entry point
+constexpr uint32_t kMdHdr = 96;        // container header bytes
+constexpr uint32_t kCpHdr = 104;       // CPC coordinate stream header bytes
+constexpr uint32_t kCvHdr = 56;        // CPC velocity stream header bytes
+
+// Keying and stream state of one MD call, in the workspace.
+struct MdCtl {
+  uint32_t B, keybits, nseg, status;  // bits per key field, key bits, segments, first error
+  uint32_t seg, digit, nk, kind;      // segment size, bits per radix digit, key fields, mode kind
+  uint32_t shift[6];                  // six-field keys: low bits dropped from each field
+  uint32_t vbits[3];                  // CPC2000: bits of each velocity lattice span
+  uint32_t keysrc;
+  uint64_t coord_bytes;               // CPC coordinate stream length
+  uint64_t vel_bytes[3];              // CPC velocity stream lengths
+  uint64_t sub_off[6], sub_len[6];    // decompression: sub-streams of the container
+  uint32_t nsub, k;
+};
+struct MdPtrs {
+  const float *f[6];
+};
+struct MdStates {
+  const FState *s[6];
+};
+struct MdSubs {
+  const uint8_t *p[6];
+  const uint64_t *len[6];   // device words holding each sub-stream's length
+};
+struct MdStatus {
+  const int32_t *s[8];
+};
 
 // ------------------------------------------------------ learned selector
 
@@ -363,6 +397,14 @@ __device__ inline T wave_sum(T v) {
 __device__ inline uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
   for (int d = kWave / 2; d >= 1; d >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, d, kWave));
+  return v;
+}
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const uint64_t o = __shfl_xor(v, d, kWave);
+    v = o < v ? o : v;
+  }
   return v;
 }
 __device__ inline uint32_t wave_max_u32(uint32_t v) {

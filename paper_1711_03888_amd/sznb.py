@@ -272,7 +272,8 @@ def profile_summary(max_kernels: int = 64):
 
 # ------------------------------------------------ molecular-dynamics modes
 
-MD_SPEED, MD_TRADEOFF, MD_COMPRESSION = 0, 1, 2
+MD_SPEED, MD_TRADEOFF, MD_COMPRESSION, MD_CPC2000 = 0, 1, 2, 3
+MD_KEY_COORD, MD_KEY_VEL, MD_KEY_ALL = 0, 1, 2
 
 
 def md_workspace_bytes(nf: int, n: int) -> int:
@@ -283,10 +284,23 @@ def md_bound(nf: int, n: int) -> int:
     return int(lib().sznb_md_bound(nf, n))
 
 
-def md_compress(fields: Sequence[torch.Tensor], eb_rel: float, md_mode: int, *, ws=None, out=None,
-                want_perm: bool = False, stream=None):
-    """Container of an MD snapshot (x, y, z[, vx, vy, vz]); returns (bytes
-    tensor, permutation or None).  Waits for the stream."""
+def md_mode(kind: int, seg_log2: int | None = None, ignored: int | None = None, key: int = 0) -> int:
+    """MD mode word: kind (MD_SPEED .. MD_CPC2000), segment 2^seg_log2
+    (10..14, default 14), ignored digits (default 6 for MD_TRADEOFF, else
+    0), key fields (MD_KEY_COORD, MD_KEY_VEL, MD_KEY_ALL)."""
+    m = kind
+    if seg_log2 is not None:
+        m |= seg_log2 << 8
+    if ignored is not None:
+        m |= (ignored + 1) << 12
+    return m | (key << 16)
+
+
+def md_compress_async(fields: Sequence[torch.Tensor], eb_rel: float, mode: int, *, ws=None, out=None, olen=None,
+                      perm=None, stream=None):
+    """Enqueues an MD compression (x, y, z[, vx, vy, vz]); returns (out,
+    device length word, workspace).  The status is read with
+    read_status(ws, 1)."""
     fields = [_field(f) for f in fields]
     nf, n = len(fields), fields[0].numel()
     if any(f.numel() != n for f in fields):
@@ -297,17 +311,30 @@ def md_compress(fields: Sequence[torch.Tensor], eb_rel: float, md_mode: int, *, 
         ws = workspace(wsb, dev)
     if out is None:
         out = torch.empty(md_bound(nf, n), dtype=torch.uint8, device=dev)
-    olen = torch.zeros(1, dtype=torch.int64, device=dev)
-    perm = torch.empty(n, dtype=torch.int32, device=dev) if want_perm else None
-    rc = lib().sznb_md_compress(nf, _arr(_vp, [f.data_ptr() for f in fields]), n, float(eb_rel), int(md_mode),
+    if olen is None:
+        olen = torch.zeros(1, dtype=torch.int64, device=dev)
+    rc = lib().sznb_md_compress(nf, _arr(_vp, [f.data_ptr() for f in fields]), n, float(eb_rel), int(mode),
                                 out.data_ptr(), out.numel(), olen.data_ptr(),
                                 perm.data_ptr() if perm is not None else None, ws.data_ptr(), ws.numel(),
                                 _stream(stream))
     _check(rc, "md_compress")
+    return out, olen, ws
+
+
+def md_compress(fields: Sequence[torch.Tensor], eb_rel: float, md_mode: int, *, ws=None, out=None,
+                want_perm: bool = False, stream=None):
+    """Container of an MD snapshot; returns (bytes tensor, permutation or
+    None).  Waits for the stream and raises on a device error."""
+    n = fields[0].numel()
+    perm = torch.empty(n, dtype=torch.int32, device=fields[0].device) if want_perm else None
+    out, olen, ws = md_compress_async(fields, eb_rel, md_mode, ws=ws, out=out, perm=perm, stream=stream)
+    first, _ = read_status(ws, 1, stream)
+    _check(first, "md_compress")
     return out[:int(olen.item())], perm
 
 
-def md_decompress(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, stream=None):
+def md_decompress_async(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, stream=None):
+    """Enqueues an MD decompression; returns (outputs, workspace)."""
     if blob.dtype != torch.uint8 or not blob.is_cuda or not blob.is_contiguous():
         raise ValueError("container must be a contiguous uint8 CUDA tensor")
     dev = blob.device
@@ -319,6 +346,15 @@ def md_decompress(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, st
     rc = lib().sznb_md_decompress(blob.data_ptr(), blob.numel(), nf, n, _arr(_vp, [o.data_ptr() for o in outs]),
                                   ws.data_ptr(), ws.numel(), _stream(stream))
     _check(rc, "md_decompress")
+    return outs, ws
+
+
+def md_decompress(blob: torch.Tensor, nf: int, n: int, *, ws=None, outs=None, stream=None):
+    """The particles of an MD container (in its stored order); waits for
+    the stream and raises on a device error."""
+    outs, ws = md_decompress_async(blob, nf, n, ws=ws, outs=outs, stream=stream)
+    first, _ = read_status(ws, 1, stream)
+    _check(first, "md_decompress")
     return outs
 
 

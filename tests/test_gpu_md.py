@@ -94,7 +94,38 @@ def test_md_corrupt_container_is_rejected():
     assert outs[0].numel() == n
 
 
-@pytest.mark.parametrize("mode", [sznb.MD_SPEED, sznb.MD_TRADEOFF, sznb.MD_COMPRESSION])
+@pytest.mark.parametrize("mode", [sznb.MD_CPC2000, sznb.md_mode(sznb.MD_TRADEOFF, 12, 0, sznb.MD_KEY_VEL),
+                                  sznb.md_mode(sznb.MD_TRADEOFF, 12, 0, sznb.MD_KEY_ALL),
+                                  sznb.md_mode(sznb.MD_TRADEOFF, 10, 4), sznb.md_mode(sznb.MD_TRADEOFF, 13, 2),
+                                  sznb.md_mode(sznb.MD_COMPRESSION, 11), sznb.md_mode(sznb.MD_CPC2000, 12)])
+def test_md_variants(mode):
+    # segment sizes, ignored digits, velocity and six-field keys, CPC2000
+    # velocities: two full 16384-particle segments and a ragged one
+    snap = datagen.md_lattice(cells=(16, 16, 36), seed=4, velocities=True)
+    _run(list(snap.values()), 1e-4, mode, "variant %#x" % mode)
+
+
+@pytest.mark.parametrize("mode", [sznb.md_mode(sznb.MD_TRADEOFF, 12, 0, sznb.MD_KEY_COORD),
+                                  sznb.md_mode(sznb.MD_TRADEOFF, 12, 0, sznb.MD_KEY_VEL),
+                                  sznb.md_mode(sznb.MD_TRADEOFF, 12, 0, sznb.MD_KEY_ALL), sznb.MD_CPC2000])
+def test_cosmology_rindex_variants(mode):
+    # the cosmology R-index studies (Table 6: segments of 4096) on a
+    # 2^16-particle snapshot
+    snap = datagen.cosmology(1 << 16, seed=9)
+    _run([snap[k] for k in datagen.FIELD_NAMES], 1e-4, mode, "cosmology %#x" % mode)
+
+
+def test_md_velocity_keys_need_six_fields():
+    snap = datagen.md_lattice(cells=(8, 8, 8), seed=3)
+    dev = [torch.from_numpy(v).cuda() for v in snap.values()]
+    for bad in (sznb.md_mode(sznb.MD_TRADEOFF, key=sznb.MD_KEY_VEL), sznb.md_mode(sznb.MD_COMPRESSION, key=1),
+                sznb.md_mode(sznb.MD_SPEED, 12), sznb.md_mode(sznb.MD_TRADEOFF, 9), 4):
+        with pytest.raises(sznb.SznbError) as e:
+            sznb.md_compress(dev, 1e-4, bad)
+        assert e.value.code == sznb.EINVAL
+
+
+@pytest.mark.parametrize("mode", [sznb.MD_SPEED, sznb.MD_TRADEOFF, sznb.MD_COMPRESSION, sznb.MD_CPC2000])
 def test_md_full_size(mode):
     # the benched FCC snapshot: 2^21 atoms, 128 segments of 16384
     snap = datagen.md_lattice()
