@@ -274,6 +274,7 @@ def profile_summary(max_kernels: int = 64):
 
 MD_SPEED, MD_TRADEOFF, MD_COMPRESSION, MD_CPC2000 = 0, 1, 2, 3
 MD_KEY_COORD, MD_KEY_VEL, MD_KEY_ALL = 0, 1, 2
+MD_HEADER_BYTES = 96
 
 
 def md_workspace_bytes(nf: int, n: int) -> int:
