@@ -56,7 +56,8 @@ def measured_traffic(kernel, tag):
 
 
 def md_modes(dev, eb, reps):
-    """The three MD modes on the 2M-atom FCC snapshot: GB/s and ratio."""
+    """The MD modes on the 2M-atom FCC snapshot: GB/s, ratio and HBM
+    fraction (enqueued back to back, no host waits inside the timing)."""
     import torch
 
     from paper_1711_03888_amd import datagen, sznb
@@ -66,6 +67,7 @@ def md_modes(dev, eb, reps):
     ws = sznb.workspace(sznb.md_workspace_bytes(3, n), dev)
     out = torch.empty(sznb.md_bound(3, n), dtype=torch.uint8, device=dev)
     outs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(3)]
+    olen = torch.zeros(1, dtype=torch.int64, device=dev)
     res = {}
     for mode, name in ((0, "best_speed"), (1, "best_tradeoff"), (2, "best_compression"), (3, "cpc2000")):
         blob, _ = sznb.md_compress(fields, eb, mode, ws=ws, out=out)
@@ -73,16 +75,28 @@ def md_modes(dev, eb, reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            blob, _ = sznb.md_compress(fields, eb, mode, ws=ws, out=out)
+            sznb.md_compress_async(fields, eb, mode, ws=ws, out=out, olen=olen)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        first, _ = sznb.read_status(ws, 1)
+        assert first == sznb.OK and int(olen.item()) == blob.numel(), (name, first)
         for _ in range(reps):
-            sznb.md_decompress(blob, 3, n, ws=ws, outs=outs)
+            sznb.md_decompress_async(blob, 3, n, ws=ws, outs=outs)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        first, _ = sznb.read_status(ws, 1)
+        assert first == sznb.OK, (name, first)
+        c_s, d_s = (t1 - t0) / reps, (t2 - t1) / reps
+        # algorithmic bytes: read the fields, write the container; a reordering
+        # also reads every field and the key fields once more and writes the
+        # reordered fields
+        cb = 12.0 * n + blob.numel() + (36.0 * n if mode else 0.0)
+        db = 12.0 * n + blob.numel()
         res[name] = {"ratio": round(12.0 * n / blob.numel(), 4),
-                     "compress_GBps": round(12.0 * n * reps / (t1 - t0) / 1e9, 2),
-                     "decompress_GBps": round(12.0 * n * reps / (t2 - t1) / 1e9, 2)}
+                     "compress_GBps": round(12.0 * n / c_s / 1e9, 2),
+                     "decompress_GBps": round(12.0 * n / d_s / 1e9, 2),
+                     "compress_hbm_frac": round(cb / c_s / 1e9 / HBM_PEAK_GBPS, 5),
+                     "decompress_hbm_frac": round(db / d_s / 1e9 / HBM_PEAK_GBPS, 5)}
     res["workload"] = "FCC lattice %d atoms x 3 float32 coordinates, eb_rel %g" % (n, eb)
     return res
 
@@ -150,6 +164,33 @@ def config1_steady(dev, walk, reps):
     n, nf = 1 << 20, 256
     fields = [torch.from_numpy(f).to(dev) for f in datagen.steady_fields(walk, n, nf)]
     mode = sznb.PRED_LV | sznb.EB_REL
+    # single-call latency: one eager compression and one eager decompression
+    # of one field, from the host call to the stream's completion
+    f0 = fields[0]
+    cap = sznb.compress_bound(n, mode)
+    o1 = torch.empty(cap, dtype=torch.uint8, device=dev)
+    l1 = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws1 = sznb.workspace(sznb.compress_workspace_bytes([n], [mode]), dev)
+    wsd1 = sznb.workspace(sznb.decompress_workspace_bytes([n]), dev)
+    r1 = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def eager_c():
+        sznb.compress_batch_async([f0], 1e-4, mode, caps=[cap], ws=ws1, outs=[o1], lens=l1)
+        torch.cuda.synchronize()
+    eager_c()
+    s1 = o1[:int(l1.item())]
+
+    def eager_d():
+        sznb.decompress_batch_async([s1], [n], outs=[r1], ws=wsd1)
+        torch.cuda.synchronize()
+    eager_d()
+    lat_c = _median_time(eager_c, 21) * 1e3
+    lat_d = _median_time(eager_d, 21) * 1e3
+    one = 4.0 * n
+    single = {"compress_ms": round(lat_c, 4), "decompress_ms": round(lat_d, 4),
+              "compress_GBps": _gbps(one, lat_c), "decompress_GBps": _gbps(one, lat_d),
+              "compress_hbm_frac": round((one + s1.numel()) / (lat_c * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5),
+              "decompress_hbm_frac": round((one + s1.numel()) / (lat_d * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5)}
     plan = sznb.CompressPlan(fields, 1e-4, mode)
     side = torch.cuda.Stream()
     # one eager launch under the library's event profiler: per-kernel times
@@ -204,7 +245,8 @@ def config1_steady(dev, walk, reps):
             "compress_hbm_frac": round((raw + comp) / (c_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "decompress_hbm_frac": round((raw + comp) / (d_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "compress_ms": round(c_ms, 4), "decompress_ms": round(d_ms, 4),
-            "kernels_ms": {"compress": kern_c, "decompress": kern_d}}
+            "kernels_ms": {"compress": kern_c, "decompress": kern_d},
+            "single_call": single}
 
 
 def batched_512(dev, walk, cosmo, reps):
@@ -267,6 +309,62 @@ def batched_512(dev, walk, cosmo, reps):
             "graph_ms": round(g_ms, 3), "per_field_ms": round(p_ms, 3)}
 
 
+def _median_time(fn, reps):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[len(ts) // 2]
+
+
+def cpu_baseline(host, eb, mode, m, dev, reps=5):
+    """The oracle (compress + decompress) on the first m values of each field:
+    median of `reps` runs on one host core, the same with one thread per
+    field (the oracle's C calls release the interpreter lock), and the
+    256 x 2^20 steady-state workload's field size (one 2^20-value random
+    walk, LV).  The GPU's bytes for the same sample must be identical."""
+    import concurrent.futures as cf
+
+    import oracle
+    import torch
+
+    from paper_1711_03888_amd import datagen, sznb
+    sample = [h[:m].copy() for h in host]
+    streams = {}
+
+    def one(i):
+        s = oracle.compress(sample[i], eb, mode)
+        oracle.decompress(s)
+        streams[i] = s
+
+    def serial():
+        for i in range(len(sample)):
+            one(i)
+    t1 = _median_time(serial, reps)
+    threads = min(len(sample), os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(threads) as ex:
+        tp = _median_time(lambda: list(ex.map(one, range(len(sample)))), reps)
+    got = sznb.compress_batch([torch.from_numpy(x).to(dev) for x in sample], eb, mode)
+    exact = all(bytes(g.cpu().numpy()) == streams[i] for i, g in enumerate(got))
+    walk = datagen.random_walk()
+    c1mode = sznb.PRED_LV | sznb.EB_REL
+
+    def c1():
+        oracle.decompress(oracle.compress(walk, 1e-4, c1mode))
+    tc1 = _median_time(c1, reps)
+    raw = 4.0 * m * len(sample)
+    return {"value": round(raw / t1 / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d values of each of the 6 fields, compress + decompress, median of %d runs "
+                      "(%.2fs each)" % (m, reps, t1),
+            "all_cores": {"value": round(raw / tp / 1e9, 5), "cores": threads,
+                          "how": "one thread per field, median of %d" % reps},
+            "steady_state_field": {"value": round(4.0 * walk.size / tc1 / 1e9, 5), "cores": 1,
+                                   "sample": "one 2^20-value random walk, LV, eb_rel 1e-4, compress + decompress, "
+                                             "median of %d" % reps},
+            "host_cores": os.cpu_count(), "gpu_bytes_identical_on_sample": exact}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,7 +374,7 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-4)
     ap.add_argument("--block-log2", type=int, default=12)
     ap.add_argument("--policy", default="bestfit", choices=["lv", "lcf", "bestfit"])
-    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="values per field timed on the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="values per field timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-md", action="store_true", help="skip the MD-mode measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector measurement")
@@ -410,23 +508,7 @@ def main():
         out["md_modes"] = md_modes(dev, args.eb, 5)
 
     if not args.no_cpu_baseline:
-        import oracle
-        m = min(args.cpu_sample, n)
-        sample = [h[:m].copy() for h in host]
-        t1 = time.perf_counter()
-        streams = [oracle.compress(s, args.eb, mode) for s in sample]
-        t2 = time.perf_counter()
-        for s in streams:
-            oracle.decompress(s)
-        t3 = time.perf_counter()
-        # the same sample through the GPU path must give the same bytes
-        got = sznb.compress_batch([torch.from_numpy(s).to(dev) for s in sample], args.eb, mode)
-        exact = all(bytes(g.cpu().numpy()) == r for g, r in zip(got, streams))
-        out["cpu_baseline"] = {"value": round(4.0 * m * len(sample) / (t3 - t1) / 1e9, 5), "unit": "GB/s",
-                               "cores": 1, "kind": "oracle",
-                               "sample": "first %d values of each of the 6 fields, compress + decompress "
-                                         "(compress %.2fs, decompress %.2fs)" % (m, t2 - t1, t3 - t2),
-                               "gpu_bytes_identical_on_sample": exact}
+        out["cpu_baseline"] = cpu_baseline(host, args.eb, mode, min(args.cpu_sample, n), dev)
     print(json.dumps(out))
 
 

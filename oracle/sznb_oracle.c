@@ -625,6 +625,20 @@ int sznbref_decompress(const uint8_t *s, size_t slen, float **out, uint64_t *n_o
     uint64_t off_pred = get_u64(s, 80), off_pfirst = get_u64(s, 88), off_cwords = get_u64(s, 96);
     uint64_t off_nesc = get_u64(s, 104), off_books = get_u64(s, 112), off_payload = get_u64(s, 120);
     if (off_payload + 4 * pw > total || off_books > off_payload) { free(y); return E_CORRUPT; }
+    /* the block tables must sit where the writer puts them: a corrupt offset
+     * would send the table reads below outside the stream */
+    {
+        uint64_t e = HDR, e_pred = 0;
+        if (policy >= 2) { e_pred = e; e = align8(e + nb); }
+        uint64_t e_pfirst = e; e = align8(e + 4 * nb);
+        uint64_t e_cwords = e; e = align8(e + 2 * nb);
+        uint64_t e_nesc = e; e = align8(e + 2 * nb);
+        if (off_pred != e_pred || off_pfirst != e_pfirst || off_cwords != e_cwords || off_nesc != e_nesc ||
+            off_books != e) {
+            free(y);
+            return E_CORRUPT;
+        }
+    }
 
     /* canonical decoding tables: first code and first index per length */
     book_t bk[3];
