@@ -1320,36 +1320,10 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
     const uint32_t skw = skip_words(cwn, st->maxlen[pred]);
     const uint64_t words = (uint64_t)skw + cwn + tesc;
 
-    // decoupled look-back over the field's earlier blocks, 64 at a time by
-    // wave 0: sum the aggregates back to the nearest published prefix
-    if (w == 0) {
-      const uint32_t lane = lane_id();
-      uint64_t P = 0;
-      if (b == 0) {
-        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[0], kFlagPre | words);
-      } else {
-        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[b], kFlagAgg | words);
-        int64_t base = (int64_t)b - 1;
-        for (;;) {
-          const int64_t j = base - (int64_t)lane;
-          const uint64_t v = j >= 0 ? ld_relaxed_u64(&G(c.lbflag)[j]) : kFlagPre;
-          const uint64_t pre = __ballot((v >> 62) == 2);
-          const uint64_t zero = __ballot(v == 0);
-          if (pre) {
-            const uint32_t pl = (uint32_t)__builtin_ctzll(pre);
-            const uint64_t upto = pl == 63 ? ~0ull : ((2ull << pl) - 1);
-            if (zero & upto) { __builtin_amdgcn_s_sleep(1); continue; }
-            P += wave_sum((unsigned long long)(lane <= pl ? (v & kValMask) : 0ull));
-            break;
-          }
-          if (zero) { __builtin_amdgcn_s_sleep(1); continue; }
-          P += wave_sum((unsigned long long)(v & kValMask));
-          base -= kWave;
-        }
-        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[b], kFlagPre | (P + words));
-      }
-      if (lane == 0) s_prefix = P;
-    }
+    // the block's own size is published at once (an inclusive prefix for
+    // the field's first block); the look-back itself runs after the packing
+    // below, so the other waves pack while wave 0 resolves it
+    if (t == 0) st_relaxed_u64(&G(c.lbflag)[b], (b == 0 ? kFlagPre : kFlagAgg) | words);
     for (uint32_t i = t; i < skw + cwn; i += kThreads) s_words[i] = 0u;
     __syncthreads();
     // skip table entries of the range starts inside this thread's bits
@@ -1401,6 +1375,33 @@ __global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__
         }
       }
       if (bits && na) atomicOr(&s_code[wi], (uint32_t)(acc >> 32));
+    }
+    // decoupled look-back over the field's earlier blocks, 64 at a time by
+    // wave 0: sum the aggregates back to the nearest published prefix
+    if (w == 0) {
+      const uint32_t lane = lane_id();
+      uint64_t P = 0;
+      if (b > 0) {
+        int64_t base = (int64_t)b - 1;
+        for (;;) {
+          const int64_t j = base - (int64_t)lane;
+          const uint64_t v = j >= 0 ? ld_relaxed_u64(&G(c.lbflag)[j]) : kFlagPre;
+          const uint64_t pre = __ballot((v >> 62) == 2);
+          const uint64_t zero = __ballot(v == 0);
+          if (pre) {
+            const uint32_t pl = (uint32_t)__builtin_ctzll(pre);
+            const uint64_t upto = pl == 63 ? ~0ull : ((2ull << pl) - 1);
+            if (zero & upto) { __builtin_amdgcn_s_sleep(1); continue; }
+            P += wave_sum((unsigned long long)(lane <= pl ? (v & kValMask) : 0ull));
+            break;
+          }
+          if (zero) { __builtin_amdgcn_s_sleep(1); continue; }
+          P += wave_sum((unsigned long long)(v & kValMask));
+          base -= kWave;
+        }
+        if (lane == 0) st_relaxed_u64(&G(c.lbflag)[b], kFlagPre | (P + words));
+      }
+      if (lane == 0) s_prefix = P;
     }
     __syncthreads();
     const uint64_t P = s_prefix;

@@ -492,9 +492,44 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
       start = s + (v >> (32u - swd));
     }
   }
-  // pass 1: count the codewords of the range
+  // Single pass for most blocks: each lane decodes its range once and keeps
+  // the symbols in registers (two per VGPR; the t-th symbol of every lane
+  // goes to the same register, so the indices are static) while it counts
+  // them; after the scan of the counts it writes them to the LDS row buffer.
+  // A range holding more than kStage codewords, or a codebook decoded with
+  // the multi-symbol table, takes the two passes below instead (count, then
+  // decode again into the row buffer).
+  constexpr int kStage = 80;
+  uint32_t stg[kStage / 2];
   uint32_t pos = start, cnt = 0;
-  if (pos < e) {
+  bool staged = !T.multi;
+  if (staged) {
+    if (pos < e) {
+      BitReader br;
+      br_init(br, wp, cw, pos);
+#pragma unroll
+      for (int t = 0; t < kStage; t++) {
+        if (pos < e) {
+          const uint32_t r = decode_sym(T, br_peek(br));
+          const uint32_t ln = (r >> 16) & 31u;
+          if (r & kLutInvalid) invalid = 1;
+          if (t & 1) stg[t >> 1] |= (r & 0xffffu) << 16;
+          else stg[t >> 1] = r & 0xffffu;
+          pos += ln;
+          br_skip(br, ln);
+          cnt++;
+        }
+      }
+    }
+    staged = __ballot(pos < e) == 0;  // every range fitted
+    if (!staged) {
+      pos = start;
+      cnt = 0;
+      invalid = 0;
+    }
+  }
+  // pass 1: count the codewords of the range
+  if (!staged && pos < e) {
     BitReader br;
     br_init(br, wp, cw, pos);
     while (pos < e) {
@@ -519,8 +554,15 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   const uint32_t total = wave_sum(cnt);
   if (total < len) { if (l == 0) *bad_flag = 1; return; }
   const uint32_t o = wave_scan_dpp(cnt) - cnt;
-  // pass 2: emit the codes
-  {
+  if (staged) {
+#pragma unroll
+    for (int t = 0; t < kStage; t++) {
+      const uint32_t i = o + (uint32_t)t;
+      if ((uint32_t)t < cnt && i < len)
+        q16[qaddr(i)] = (uint16_t)((t & 1) ? (stg[t >> 1] >> 16) : (stg[t >> 1] & 0xffffu));
+    }
+  } else {
+    // pass 2: emit the codes
     uint32_t p = start, i = o;
     if (p < e && i < len) {
       BitReader br;
