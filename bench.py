@@ -153,20 +153,13 @@ def _gbps(nbytes, ms):
     return round(nbytes / (ms * 1e-3) / 1e9, 2)
 
 
-def config1_steady(dev, walk, reps):
-    """256 distinct random-walk fields of 2^20 values (1 GiB), LV, one
-    graph-captured batched compression and one graph-captured batched
-    decompression; HBM fraction of each on algorithmic bytes."""
+def single_call_latency(dev, f0, mode):
+    """One eager compression and one eager decompression of one field (host
+    call to stream completion), median of 21."""
     import torch
 
     from paper_1711_03888_amd import sznb
-    from paper_1711_03888_amd import datagen
-    n, nf = 1 << 20, 256
-    fields = [torch.from_numpy(f).to(dev) for f in datagen.steady_fields(walk, n, nf)]
-    mode = sznb.PRED_LV | sznb.EB_REL
-    # single-call latency: one eager compression and one eager decompression
-    # of one field, from the host call to the stream's completion
-    f0 = fields[0]
+    n = f0.numel()
     cap = sznb.compress_bound(n, mode)
     o1 = torch.empty(cap, dtype=torch.uint8, device=dev)
     l1 = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -187,10 +180,26 @@ def config1_steady(dev, walk, reps):
     lat_c = _median_time(eager_c, 21) * 1e3
     lat_d = _median_time(eager_d, 21) * 1e3
     one = 4.0 * n
-    single = {"compress_ms": round(lat_c, 4), "decompress_ms": round(lat_d, 4),
-              "compress_GBps": _gbps(one, lat_c), "decompress_GBps": _gbps(one, lat_d),
-              "compress_hbm_frac": round((one + s1.numel()) / (lat_c * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5),
-              "decompress_hbm_frac": round((one + s1.numel()) / (lat_d * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5)}
+    return {"compress_ms": round(lat_c, 4), "decompress_ms": round(lat_d, 4),
+            "compress_GBps": _gbps(one, lat_c), "decompress_GBps": _gbps(one, lat_d),
+            "compress_hbm_frac": round((one + s1.numel()) / (lat_c * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5),
+            "decompress_hbm_frac": round((one + s1.numel()) / (lat_d * 1e-3) / 1e9 / HBM_PEAK_GBPS, 5)}
+
+
+def config1_steady(dev, walk, reps, single_call=True):
+    """256 distinct random-walk fields of 2^20 values (1 GiB), LV, one
+    graph-captured batched compression and one graph-captured batched
+    decompression; HBM fraction of each on algorithmic bytes."""
+    import torch
+
+    from paper_1711_03888_amd import sznb
+    from paper_1711_03888_amd import datagen
+    n, nf = 1 << 20, 256
+    fields = [torch.from_numpy(f).to(dev) for f in datagen.steady_fields(walk, n, nf)]
+    mode = sznb.PRED_LV | sznb.EB_REL
+    # single-call latency: one eager compression and one eager decompression
+    # of one field, from the host call to the stream's completion
+    single = single_call_latency(dev, fields[0], mode) if single_call else None
     plan = sznb.CompressPlan(fields, 1e-4, mode)
     side = torch.cuda.Stream()
     # one eager launch under the library's event profiler: per-kernel times
@@ -380,6 +389,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-selector measurement")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the steady-state 256 x 1M and the 512-field batched measurements")
+    ap.add_argument("--steady-only", action="store_true",
+                    help="only the steady-state 256 x 1M measurement (for profiling it on its own)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
@@ -393,6 +404,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.steady_only:
+        walk = datagen.random_walk(1 << 28, seed=7)
+        print(json.dumps({"config1_steady": config1_steady(dev, walk, max(3, args.steps), single_call=False)}))
+        return
     t_gen = time.time()
     snap = datagen.cosmology(args.particles, seed=2)
     names = list(datagen.FIELD_NAMES)
