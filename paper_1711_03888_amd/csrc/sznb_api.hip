@@ -895,7 +895,7 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
   const uint32_t lut_words = nsym_max <= 4096 ? (2u << kLutBits) : (1u << kLutBits);
   const size_t lds_cu = (dv->lds_per_block ? dv->lds_per_block : 65536) - 1024;
   const size_t tables = 4ull * lut_words + 4ull * 64 + 8ull * 32;
-  const size_t per_wave = 2ull * (smax + smax / 32);
+  const size_t per_wave = 2ull * smax;
   // canonical symbols in LDS (long codes resolve without a global read) or
   // in global memory (more waves per CU): the layout with more resident
   // waves wins, LDS symbols on a tie

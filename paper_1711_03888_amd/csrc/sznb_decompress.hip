@@ -261,8 +261,16 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
     for (uint32_t l = 1; l <= ml; l++) len += s_limit[l] <= win;
     uint32_t ent;
     if (len > ml) ent = kLutInvalid | 0xffffu | (1u << 16);
-    else if (len > (uint32_t)kLutBits) ent = kLutLong | (len << 16);  // shortest code under this prefix
-    else {
+    else if (len > (uint32_t)kLutBits) {
+      // shortest code under this prefix; when the prefix's last window has a
+      // code of the same length, every code under it has that length and
+      // its canonical index follows from the bits after the prefix
+      const uint64_t wl = win | ((1ull << (32 - kLutBits)) - 1u);
+      uint32_t ll = 1;
+      for (uint32_t l = 1; l <= ml; l++) ll += s_limit[l] <= wl;
+      ent = kLutLong | (len << 16);
+      if (ll == len) ent |= kLutOne | (s_base[len] - s_first[len] + (e << (len - kLutBits)));
+    } else {
       const uint32_t code = (uint32_t)(win >> (32 - len));
       ent = (uint32_t)syms[s_base[len] + (code - s_first[len])] | (len << 16);
     }
@@ -415,7 +423,7 @@ __device__ inline void br_skip(BitReader &r, uint32_t len) {
 // decoding keeps going)
 __device__ inline uint32_t decode_len(const DecTab &T, uint32_t e, uint32_t win) {
   uint32_t len = (e >> 16) & 31u;
-  if (e & kLutLong) {
+  if ((e & (kLutLong | kLutOne)) == kLutLong) {
     while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
     if (len > T.maxlen) len = 1;
   }
@@ -425,11 +433,16 @@ __device__ inline uint32_t decode_len(const DecTab &T, uint32_t e, uint32_t win)
 __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
   const uint32_t e = T.lut[win >> (32 - kLutBits)];
   if (!(e & kLutLong)) return e & 0x00ffffffu;
-  uint32_t len = (e >> 16) & 31u;
-  while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
-  if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
-  const uint32_t code = win >> (32 - len);
-  const uint32_t idx = T.base[len] + (code - T.first[len]);
+  uint32_t len = (e >> 16) & 31u, idx;
+  if (e & kLutOne) {
+    // one code length under the prefix: the index is the prefix's first
+    // plus the len - kLutBits bits after the prefix
+    idx = (e & 0xffffu) + ((win << kLutBits) >> (32 + kLutBits - len));
+  } else {
+    while (len <= T.maxlen && (uint64_t)win >= T.limit[len]) len++;
+    if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
+    idx = T.base[len] + ((win >> (32 - len)) - T.first[len]);
+  }
   return (uint32_t)(T.syms_lds ? T.lsyms[idx] : T.gsyms[idx]) | (len << 16);
 }
 
@@ -437,12 +450,13 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
 // Lane l < R decodes the codewords starting in range l of the block's code
 // bits, from the first codeword the skip table points at: one pass counts
 // them, a second writes their codes after the counts of the lanes before it
-// into the wave's LDS region (u16 per element, one padding word per 64
-// elements keeps concurrent lanes on different banks).  The inverse
+// into the wave's LDS region (u16 per element; the words of row r are
+// permuted by XOR with r mod 32, so that lanes writing at the same offset
+// of consecutive rows use different banks, with no padding).  The inverse
 // prediction then runs row by row: each 64-element row is integrated with
 // one (LV), two (LCF) or three (QCF) DPP wave scans carried across rows, and
 // the reconstructed floats are stored straight from registers, coalesced.
-__device__ __forceinline__ uint32_t qaddr(uint32_t e) { return e + 2u * (e >> 6); }
+__device__ __forceinline__ uint32_t qaddr(uint32_t e) { return e ^ (((e >> 6) & 31u) << 1); }
 
 __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState> st, const DecTab &T, uint32_t b,
                                              uint16_t *q16, int *bad_flag) {
@@ -662,7 +676,7 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
 // dw waves per workgroup.  Dynamic LDS: lut (4096 words), lut2 (4096 words
 // when some codebook is small enough to use it) | first, base (32
 // words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
-// code regions of 2 (smax + smax/32) bytes.
+// code regions of 2 smax bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
                          uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket, uint32_t lut_words) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -741,7 +755,7 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     if (idx < st->grp_count[k]) {
       const uint32_t b = G(df.order)[st->grp_start[k] + idx];
       int bad = 0;
-      decode_block(df, st, T2, b, reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * (smax + smax / 32u)), &bad);
+      decode_block(df, st, T2, b, reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * smax), &bad);
       if (bad && lane_id() == 0) atomicCAS(&df.st->status, 0, SZNB_ECORRUPT);
     }
   }

@@ -190,7 +190,11 @@ struct alignas(16) DField {
 };
 constexpr int kSlowWords = 128;
 
-// decode-table entry: sym | len << 16; flags
+// decode-table entry: sym | len << 16; flags.  A long entry (a prefix of
+// codes longer than the table's bits) holds the shortest length under the
+// prefix; with kLutOne every code under the prefix has that length and bits
+// 0-15 hold the canonical index of the prefix's first code.
+constexpr uint32_t kLutOne = 1u << 21;
 constexpr uint32_t kLutLong = 1u << 22;
 constexpr uint32_t kLutInvalid = 1u << 23;
 
