@@ -429,7 +429,11 @@ __device__ inline uint32_t decode_len(const DecTab &T, uint32_t e, uint32_t win)
   }
   return len;
 }
-// symbol | length << 16 (plus the invalid flag for a pattern that is no codeword)
+// symbol | length << 16 (plus the invalid flag for a pattern that is no
+// codeword).  kLds: the canonical symbols are known to be in LDS, so that no
+// symbol read can come from global memory (such a read would make every
+// symbol wait for the bit reader's read-ahead loads as well).
+template <bool kLds = false>
 __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
   const uint32_t e = T.lut[win >> (32 - kLutBits)];
   if (!(e & kLutLong)) return e & 0x00ffffffu;
@@ -443,7 +447,7 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
     if (len > T.maxlen) return kLutInvalid | 0xffffu | (1u << 16);
     idx = T.base[len] + ((win >> (32 - len)) - T.first[len]);
   }
-  return (uint32_t)(T.syms_lds ? T.lsyms[idx] : T.gsyms[idx]) | (len << 16);
+  return (uint32_t)(kLds || T.syms_lds ? T.lsyms[idx] : T.gsyms[idx]) | (len << 16);
 }
 
 // One wave decodes block b of a stream and stores its floats.
@@ -510,13 +514,13 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   // the symbols in registers (two per VGPR; the t-th symbol of every lane
   // goes to the same register, so the indices are static) while it counts
   // them; after the scan of the counts it writes them to the LDS row buffer.
-  // A range holding more than kStage codewords, or a codebook decoded with
-  // the multi-symbol table, takes the two passes below instead (count, then
-  // decode again into the row buffer).
+  // A range holding more than kStage codewords, a codebook decoded with the
+  // multi-symbol table, or canonical symbols left in global memory take the
+  // two passes below instead (count, then decode again into the row buffer).
   constexpr int kStage = 80;
   uint32_t stg[kStage / 2];
   uint32_t pos = start, cnt = 0;
-  bool staged = !T.multi;
+  bool staged = !T.multi && T.syms_lds;
   if (staged) {
     if (pos < e) {
       BitReader br;
@@ -524,7 +528,7 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
 #pragma unroll
       for (int t = 0; t < kStage; t++) {
         if (pos < e) {
-          const uint32_t r = decode_sym(T, br_peek(br));
+          const uint32_t r = decode_sym<true>(T, br_peek(br));
           const uint32_t ln = (r >> 16) & 31u;
           if (r & kLutInvalid) invalid = 1;
           if (t & 1) stg[t >> 1] |= (r & 0xffffu) << 16;
