@@ -57,7 +57,9 @@ __global__ void cpc_offsets(const uint32_t *, uint32_t, uint64_t, const MdCtl *,
 template <bool kOffset>
 __global__ void cpc_pack(const uint64_t *, uint64_t, const MdCtl *, const uint32_t *, const uint32_t *,
                          const uint32_t *, const uint32_t *, const uint64_t *, uint8_t *);
-__global__ void cpc_decode(const uint8_t *, const MdCtl *, uint64_t, float *, float *, float *, int *);
+__global__ void cpc_decode(const uint8_t *, const MdCtl *, uint64_t, uint64_t *, uint64_t *, int *);
+__global__ void cpc_coords(const uint8_t *, const MdCtl *, uint64_t, const uint64_t *, const uint64_t *, float *,
+                           float *, float *, const int *);
 __global__ void cpv_decode(const uint8_t *, const MdCtl *, int, uint64_t, float *, int *);
 __global__ void md_assemble(uint8_t *, uint64_t, uint64_t *, MdSubs, int, int, uint64_t, const MdCtl *, int *);
 __global__ void md_parse(const uint8_t *, uint64_t, int, uint64_t, MdCtl *, DField *, int *);
@@ -1225,7 +1227,11 @@ static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_
   rc = decompress_run(P, s);
   if (rc) return rc;
   const unsigned gmax = (unsigned)L.nseg_max;  // the smallest segment size's count: extra workgroups return
-  SZNB_LAUNCH("cpc_decode", cpc_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, n, outs[0], outs[1], outs[2], cstat);
+  // relative keys and the bases of every 256 keys (n / 256 + 1 entries at most)
+  uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys0), *kbase = reinterpret_cast<uint64_t *>(ws + L.keys1);
+  SZNB_LAUNCH("cpc_decode", cpc_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, n, keys, kbase, cstat);
+  SZNB_LAUNCH("cpc_coords", cpc_coords, dim3(dv->cus * 8), dim3(256), 0, s, in, ctl, n, keys, kbase, outs[0],
+              outs[1], outs[2], cstat);
   for (int j = 0; j + 3 < nf; j++)
     SZNB_LAUNCH("cpv_decode", cpv_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, j, n, outs[3 + j], cstat);
   MdStatus ss{};

@@ -24,7 +24,8 @@
 //   cpc_offsets segment word offsets, stream header
 //   cpc_pack    per segment: first key or minimum, parameter, Rice codes
 //   cpc_decode  one wave per segment, one lane per 256 keys (entry points
-//               stored in the stream): keys back, then lattice values
+//               stored in the stream): keys back
+//   cpc_coords  keys -> coordinates
 //   cpv_decode  the same for a velocity stream (one pass: no prefix sums)
 //   md_assemble container header and sub-stream copies
 //   md_parse    container header -> sub-stream descriptors (decompression)
@@ -486,8 +487,9 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *val, uint64_t n,
 
 // Per-lane bit reader over one segment's words (LDS or global, chosen once
 // per segment): a 64-bit window holding the bits from pos on (more than 32
-// of them after every refill); words past the segment read as zero and a
-// read that would pass nbits marks the segment corrupt.
+// of them after every refill) and the next word, read one refill ahead so
+// that a refill never waits for its load; words past the segment read as
+// zero and a read that would pass nbits marks the segment corrupt.
 template <bool kL>
 struct SegReader {
   const uint32_t *lw;
@@ -495,6 +497,7 @@ struct SegReader {
   uint64_t nw, nbits, pos, buf, wi;
   uint32_t nv;
   bool *bad;
+  uint32_t pend;  // word wi
   __device__ uint32_t word(uint64_t i) const { return i >= nw ? 0u : (kL ? lw[i] : gw[i]); }
   __device__ void seek(uint64_t p) {
     pos = p;
@@ -504,15 +507,17 @@ struct SegReader {
     buf = ((w0 << 32) | w1) << sh;
     nv = 64u - sh;
     wi += 2;
+    pend = word(wi);
   }
   __device__ void skip(uint32_t nb) {  // nb <= 32
     buf = nb ? buf << nb : buf;
     nv -= nb;
     pos += nb;
     if (nv <= 32u) {
-      buf |= (uint64_t)word(wi) << (32u - nv);
+      buf |= (uint64_t)pend << (32u - nv);
       nv += 32u;
       wi++;
+      pend = word(wi);
     }
   }
   __device__ uint64_t take(uint32_t nb) {  // nb <= 32
@@ -531,11 +536,46 @@ struct SegReader {
   __device__ uint64_t rice(uint32_t r, uint32_t vb) {
     const uint32_t ones = ~(uint32_t)(buf >> 32);
     const uint32_t q = ones ? (uint32_t)__clz(ones) : kEscQ;
+    if (q + r < 32u) {  // the whole code lies in the window's upper 32 bits
+      const uint32_t nb = q + 1u + r;
+      if (pos + nb > nbits) { *bad = true; return 0; }
+      const uint64_t v = ((uint64_t)q << r) | (((buf << (q + 1u)) >> 1) >> (63u - r));
+      skip(nb);
+      return v;
+    }
     const uint32_t ub = q < kEscQ ? q + 1u : kEscQ;
     if (pos + ub > nbits) { *bad = true; return 0; }
     skip(ub);
     if (q == kEscQ) return take_wide(vb);
     return ((uint64_t)q << r) | take_wide(r);
+  }
+  // The Rice codes of values i0 .. i1-1, f(v) for each.  A code that fits in
+  // the window's upper 32 bits (nearly all) is taken without a bound check:
+  // the caller compares the end position with the next entry point, and
+  // words past the segment read as zero.
+  template <class Fn>
+  __device__ void codes(uint32_t i0, uint32_t i1, uint32_t r, uint32_t vb, Fn f) {
+    for (uint32_t i = i0; i < i1; i++) {
+      const uint32_t ones = ~(uint32_t)(buf >> 32);
+      const uint32_t q = ones ? (uint32_t)__clz(ones) : kEscQ;
+      uint64_t v;
+      if (q + r < 32u) {
+        const uint32_t nb = q + 1u + r;
+        v = ((uint64_t)q << r) | (((buf << (q + 1u)) >> 1) >> (63u - r));
+        buf <<= nb;
+        nv -= nb;
+        pos += nb;
+        if (nv <= 32u) {
+          buf |= (uint64_t)pend << (32u - nv);
+          nv += 32u;
+          wi++;
+          pend = word(wi);
+        }
+      } else {
+        v = rice(r, vb);
+      }
+      f(v);
+    }
   }
 };
 
@@ -560,14 +600,15 @@ __device__ inline void stage_words(uint32_t *s_seg, gptr<const uint32_t> gw, uin
 __device__ inline bool seg_size_ok(uint32_t S) { return S >= 1024u && S <= kMdSegMax && !(S & (S - 1)); }
 
 // One wave per segment, one lane per 256 keys: each lane starts at its entry
-// point, sums its deltas (pass 1), the wave scans the sums, and each lane
-// decodes again writing keys and coordinates (pass 2).  Every read is checked
+// point and writes the running sums of its deltas to kout; the wave scans the
+// lanes' totals into kbase (one entry per 256 keys: key i is kout[i] +
+// kbase[i / 256]).  Every read is checked
 // against the segment's bit count and the stream length, and every lane must
 // end exactly at the next lane's entry point; a stream that fails a check
 // sets ECORRUPT.  The stream is sub-stream 0 of the container (offset and
 // length from md_parse); the grid covers the smallest segment size.
-__global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdCtl *ctl, uint64_t n, float *ox,
-                                                    float *oy, float *oz, int *status) {
+__global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdCtl *ctl, uint64_t n, uint64_t *kout,
+                                                    uint64_t *kbase, int *status) {
   if (ctl->status || ctl->kind < 2) return;
   const uint8_t *cs = in + ctl->sub_off[0];
   const uint64_t cs_len = ctl->sub_len[0];
@@ -587,14 +628,6 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
   const uint64_t etab = kCpHdr + align8(4ull * nseg);
   const uint64_t tab = etab + align8(4ull * cpc_entries(n, S));
   if (seg >= nseg) return;
-  float mn[3];
-  double step[3];
-  for (int c = 0; c < 3; c++) {
-    mn[c] = *reinterpret_cast<const float *>(cs + 28 + 8 * c);
-    const uint64_t lo = *reinterpret_cast<const uint32_t *>(cs + 76 + 8 * c);
-    const uint64_t hi = *reinterpret_cast<const uint32_t *>(cs + 80 + 8 * c);
-    step[c] = __longlong_as_double((long long)(lo | (hi << 32)));
-  }
   const gptr<const uint32_t> sb = G(reinterpret_cast<const uint32_t *>(cs + kCpHdr));
   uint64_t woff = 0;
   for (uint32_t s = lane; s < seg; s += kWave) woff += (sb[s] + 31) / 32;
@@ -630,43 +663,66 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
     const uint64_t start = active ? ent[lane] : 0;
     const uint64_t stop = (k1 < m) ? ent[lane + 1] : nbits;
     if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
-    auto next = [&](uint32_t i) -> uint64_t {  // delta of key i (the raw key for i = 0)
-      if (i == 0) { const uint64_t k = R.take_wide(kb); (void)R.take(6); return k; }
-      return R.rice(r, kb);
+    // the segment's first key is stored raw (before the Rice parameter)
+    const auto first = [&]() -> uint64_t {
+      const uint64_t k = R.take_wide(kb);
+      (void)R.take(6);
+      return k;
     };
-    // pass 1: sum of this lane's deltas
+    // one pass: each lane writes its keys relative to its first key's
+    // predecessor (the running sum of its deltas) and its total; the wave's
+    // exclusive scan of the totals gives every lane's base, which cpc_coords
+    // adds back (global stores: flat stores in flight would hold up every
+    // LDS refill of the bit reader)
     uint64_t sum = 0;
     if (active && !bad) {
       R.seek(start);
-      for (uint32_t i = k0; i < k1 && !bad; i++) sum += next(i);
+      gptr<uint64_t> gk = G(kout) + base + k0;
+      if (k0 == 0) *gk++ = sum = first();
+      R.codes(k0 == 0 ? 1u : k0, k1, r, kb, [&](uint64_t v) {
+        sum += v;
+        *gk++ = sum;
+      });
       if (R.pos != stop) bad = true;
     }
-    // exclusive prefix of the lane sums
     uint64_t inc = sum;
     for (int d = 1; d < kWave; d <<= 1) {
       const uint64_t o = __shfl_up(inc, d, kWave);
       if ((int)lane >= d) inc += o;
     }
-    const bool any_bad = __ballot(bad) != 0;
-    if (any_bad) {
+    if (__ballot(bad) != 0) {
       if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
       return;
     }
-    // pass 2: keys and coordinates (global stores: flat stores in flight
-    // would hold up every LDS refill of the bit reader)
-    if (!active) return;
-    uint64_t k = inc - sum;
-    R.seek(start);
-    const gptr<float> gx = G(ox), gy = G(oy), gz = G(oz);
-    for (uint32_t i = k0; i < k1; i++) {
-      k += next(i);
-      const uint32_t px = compact3(k >> 2), py = compact3(k >> 1), pz = compact3(k);
-      gx[base + i] = (float)fma((double)(int32_t)px, step[0], (double)mn[0]);
-      gy[base + i] = (float)fma((double)(int32_t)py, step[1], (double)mn[1]);
-      gz[base + i] = (float)fma((double)(int32_t)pz, step[2], (double)mn[2]);
-    }
+    if (active) G(kbase)[base / kMdSub + lane] = inc - sum;
   };
   if (in_lds) run(std::true_type{}); else run(std::false_type{});
+}
+
+// The decoded keys back to coordinates (key i = kout[i] + kbase[i / 256]),
+// x~ = fl32(fma(p, step, mn)) of each coordinate's lattice index (the bits of the key at its place in every
+// 3-bit digit), after cpc_decode, over the whole grid.  Nothing is written
+// for a container that failed a check.
+__global__ void cpc_coords(const uint8_t *in, const MdCtl *ctl, uint64_t n, const uint64_t *key,
+                           const uint64_t *kbase, float *ox, float *oy, float *oz, const int *status) {
+  if (ctl->status || ctl->kind < 2 || *status || ctl->sub_len[0] < kCpHdr) return;
+  const uint8_t *cs = in + ctl->sub_off[0];
+  float mn[3];
+  double step[3];
+  for (int c = 0; c < 3; c++) {
+    mn[c] = *reinterpret_cast<const float *>(cs + 28 + 8 * c);
+    const uint64_t lo = *reinterpret_cast<const uint32_t *>(cs + 76 + 8 * c);
+    const uint64_t hi = *reinterpret_cast<const uint32_t *>(cs + 80 + 8 * c);
+    step[c] = __longlong_as_double((long long)(lo | (hi << 32)));
+  }
+  const gptr<const uint64_t> gk = G(key), gb = G(kbase);
+  const gptr<float> gx = G(ox), gy = G(oy), gz = G(oz);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = gk[i] + gb[i / kMdSub];
+    gx[i] = (float)fma((double)(int32_t)compact3(k >> 2), step[0], (double)mn[0]);
+    gy[i] = (float)fma((double)(int32_t)compact3(k >> 1), step[1], (double)mn[1]);
+    gz[i] = (float)fma((double)(int32_t)compact3(k), step[2], (double)mn[2]);
+  }
 }
 
 // CPC2000 velocity stream (sub-stream 1 + j of the container): one wave per
@@ -734,11 +790,10 @@ __global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdC
     }
     if (!active) return;
     R.seek(start);
-    const gptr<float> go = G(out);
-    for (uint32_t i = v0; i < v1 && !bad; i++) {
-      const uint64_t p = vmin + R.rice(r, vb);
-      go[base + i] = (float)fma((double)(int32_t)(uint32_t)p, step, (double)mn);
-    }
+    gptr<float> go = G(out) + base + v0;
+    R.codes(v0, v1, r, vb, [&](uint64_t v) {
+      *go++ = (float)fma((double)(int32_t)(uint32_t)(vmin + v), step, (double)mn);
+    });
     if (R.pos != stop) bad = true;
     if (__ballot(bad) && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
   };
