@@ -261,8 +261,7 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n
                                                  const uint32_t *vbp, uint32_t *seg_r, uint32_t *seg_bits,
                                                  uint64_t *seg_min) {
   __shared__ unsigned long long s_sum[kMW];
-  __shared__ unsigned long long s_best;
-  __shared__ uint32_t s_r;
+  __shared__ uint32_t s_cost[64 * kMW];
   if (ctl->status) return;
   const uint32_t seg = blockIdx.x, S = ctl->seg;
   const uint64_t base = (uint64_t)seg * S;
@@ -270,7 +269,6 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n
   const uint32_t m = (uint32_t)min((uint64_t)S, n - base);
   const uint32_t vb = *vbp;
   const int t = threadIdx.x, w = t / kWave;
-  if (t == 0) { s_best = ~0ull; s_r = 0; }
   // this thread's codes, read once (at most kMdSegMax / kMT of them)
   constexpr int kPer = kMdSegMax / kMT;
   const uint32_t first = kOffset ? 0u : 1u;
@@ -299,25 +297,29 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n
       dl[j] = i < m ? val[base + i] - val[base + i - 1] : 0u;
     }
   }
+  // every wave's cost for every parameter, then one reduction: lane r of
+  // wave 0 totals parameter r, and the wave's minimum of (cost, r) picks the
+  // cheapest, the smaller r on a tie
   for (uint32_t r = 0; r <= vb; r++) {
-    unsigned long long c = 0;
+    uint32_t c = 0;
 #pragma unroll
     for (int j = 0; j < kPer; j++)
-      if (first + t + (uint32_t)j * kMT < m) c += rice_cost(dl[j], r, vb);
+      if (first + t + (uint32_t)j * kMT < m) c += (uint32_t)rice_cost(dl[j], r, vb);
     c = wave_sum(c);
-    if (lane_id() == 0) s_sum[w] = c;
-    __syncthreads();
-    if (t == 0) {
-      unsigned long long tot = 0;
-      for (int j = 0; j < kMW; j++) tot += s_sum[j];
-      if (tot < s_best) { s_best = tot; s_r = r; }
-    }
-    __syncthreads();
+    if (lane_id() == 0) s_cost[r * kMW + w] = c;
   }
-  if (t == 0) {
-    seg_r[seg] = s_r;
-    seg_bits[seg] = (uint32_t)(vb + 6 + (m > first ? s_best : 0ull));
-    if (kOffset) seg_min[seg] = vmin;
+  __syncthreads();
+  if (w == 0) {
+    const uint32_t r = lane_id();
+    uint64_t tot = 0;
+    if (r <= vb)
+      for (int j = 0; j < kMW; j++) tot += s_cost[r * kMW + j];
+    const uint64_t best = wave_min_u64(r <= vb ? (tot << 6) | r : ~0ull);
+    if (r == 0) {
+      seg_r[seg] = (uint32_t)(best & 63u);
+      seg_bits[seg] = (uint32_t)(vb + 6 + (m > first ? (best >> 6) : 0ull));
+      if (kOffset) seg_min[seg] = vmin;
+    }
   }
 }
 
@@ -344,15 +346,23 @@ __device__ inline void put64(uint8_t *p, uint64_t o, uint64_t v) {
 template <bool kOffset>
 __global__ void cpc_offsets(const uint32_t *seg_bits, uint32_t nseg_max, uint64_t n, const MdCtl *ctl, MdStates fs,
                             int vfield, uint8_t *cs, uint32_t *seg_woff, uint64_t *len_out) {
-  if (threadIdx.x || blockIdx.x) return;
-  if (ctl->status) return;
-  const uint32_t nseg = ctl->nseg, S = ctl->seg;
-  uint32_t o = 0;
-  for (uint32_t s = 0; s < nseg && s < nseg_max; s++) {
-    seg_woff[s] = o;
-    o += (seg_bits[s] + 31) / 32;
-  }
+  if (blockIdx.x || ctl->status) return;
+  const uint32_t nseg = min(ctl->nseg, nseg_max), S = ctl->seg, l = threadIdx.x;
   const uint32_t hb = kOffset ? kCvHdr : kCpHdr;
+  // word offsets of the segments (a wave scan, 64 segments at a time) and
+  // the segments' bit counts into the stream
+  uint32_t o = 0;
+  for (uint32_t s0 = 0; s0 < nseg; s0 += kWave) {
+    const uint32_t s = s0 + l;
+    const uint32_t sbits = s < nseg ? seg_bits[s] : 0u, wds = (sbits + 31) / 32;
+    const uint32_t inc = wave_incl_scan(wds);
+    if (s < nseg) {
+      seg_woff[s] = o + inc - wds;
+      put32(cs, hb + 4ull * s, sbits);
+    }
+    o += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
+  }
+  if (l) return;
   const uint64_t tab = hb + align8((uint64_t)4 * nseg) + align8(4ull * cpc_entries(n, S));
   *len_out = tab + 4ull * o;
   for (uint32_t i = 0; i < hb; i += 4) put32(cs, i, 0u);
@@ -381,7 +391,6 @@ __global__ void cpc_offsets(const uint32_t *seg_bits, uint32_t nseg_max, uint64_
       put64(cs, 76 + 8 * c, (uint64_t)__double_as_longlong(fs.s[c]->step));
     }
   }
-  for (uint32_t s2i = 0; s2i < nseg; s2i++) put32(cs, hb + 4ull * s2i, seg_bits[s2i]);
   if (nseg & 1u) put32(cs, hb + 4ull * nseg, 0u);
   const uint64_t ne = cpc_entries(n, S);
   if (ne & 1u) put32(cs, hb + align8(4ull * nseg) + 4ull * ne, 0u);
