@@ -146,10 +146,15 @@ __device__ inline uint64_t md_lanemask_lt() {
 }
 
 // Stable sort of one segment's (key, idx) pairs by key >> (digit k), LSD on
-// 8-bit digits, ping-pong between (k0, i0) and (k1, i1); each of the 16
-// waves owns a contiguous slice and keeps its order.
+// 8-bit digits; each of the 16 waves owns a contiguous slice of the current
+// order and keeps it.  When the sorted bits and the 14-bit position in the
+// segment fit in 64 bits, every pass stays in LDS (dynamic, 8 bytes per
+// element): the packed values are scattered there and read back in the next
+// pass's order, and the keys and indices are gathered by position at the
+// end.  Otherwise each pass ping-pongs through (k0, i0) and (k1, i1).
 __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint64_t *k1, uint32_t *i1, uint64_t n,
                                                uint32_t k_ignored, const MdCtl *ctl) {
+  extern __shared__ __align__(16) uint64_t s_v[];
   __shared__ uint32_t s_cnt[256 * kMW];
   __shared__ uint32_t s_tot[kMW];
   if (ctl->status) return;
@@ -165,25 +170,17 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
   uint32_t *ia = i0 + base, *ib = i1 + base;
   const uint32_t segw = (m + kMW - 1) / kMW;
   const uint32_t beg = min(m, segw * w), end = min(m, beg + segw);
-  // the wave's keys and indices of a pass are read once, in one round trip
   constexpr int kPL = kMdSegMax / kMT;  // chunks of 64 per wave
-  for (uint32_t ps = 0; ps < passes; ps++) {
-    const uint32_t sh = shift0 + 8 * ps;
-    uint64_t kv[kPL];
-    uint32_t iv[kPL];
-#pragma unroll
-    for (int c = 0; c < kPL; c++) {
-      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
-      kv[c] = i < end ? ka[i] : 0ull;
-      iv[c] = i < end ? ia[i] : 0u;
-    }
+  // one pass over the digit at bit sh of the values get(c) (chunk c of the
+  // wave's slice): counts, the exclusive scan over (digit, wave),
+  // digit-major, then put(c, pos) for every element
+  const auto pass = [&](auto get, uint32_t sh, auto put) {
     for (uint32_t i = t; i < 256u * kMW; i += kMT) s_cnt[i] = 0;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kPL; c++)
-      if (beg + (uint32_t)c * kWave + lane_id() < end) atomicAdd(&s_cnt[((kv[c] >> sh) & 255u) * kMW + w], 1u);
+      if (beg + (uint32_t)c * kWave + lane_id() < end) atomicAdd(&s_cnt[((get(c) >> sh) & 255u) * kMW + w], 1u);
     __syncthreads();
-    // exclusive scan over (digit, wave), digit-major
     uint32_t loc = 0;
     for (int j = 0; j < 4; j++) loc += s_cnt[4 * t + j];
     const uint32_t inc = wave_incl_scan(loc);
@@ -191,13 +188,13 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
     __syncthreads();
     uint32_t run = inc - loc;
     for (int j = 0; j < w; j++) run += s_tot[j];
-    for (int j = 0; j < 4; j++) { const uint32_t v = s_cnt[4 * t + j]; s_cnt[4 * t + j] = run; run += v; }
+    for (int j = 0; j < 4; j++) { const uint32_t x = s_cnt[4 * t + j]; s_cnt[4 * t + j] = run; run += x; }
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < kPL; c++) {
       const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
       const bool valid = i < end;
-      const uint32_t dg = (uint32_t)((kv[c] >> sh) & 255u);
+      const uint32_t dg = valid ? (uint32_t)((get(c) >> sh) & 255u) : 0u;
       uint64_t mk = __ballot(valid);
       for (int bt = 0; bt < 8; bt++) {
         const uint64_t bb = __ballot(valid && ((dg >> bt) & 1u));
@@ -208,13 +205,51 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
       if (valid) pos = s_cnt[dg * kMW + w] + rank;
       __builtin_amdgcn_wave_barrier();
       if (valid) {
-        kb[pos] = kv[c];
-        ib[pos] = iv[c];
+        put(c, pos);
         if (rank == cnt - 1) s_cnt[dg * kMW + w] += cnt;
       }
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
+  };
+  if (bits + 14u <= 64u) {
+    uint64_t v[kPL];
+#pragma unroll
+    for (int c = 0; c < kPL; c++) {
+      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
+      v[c] = i < end ? (((ka[i] >> shift0) << 14) | i) : 0ull;
+    }
+    for (uint32_t ps = 0; ps < passes; ps++) {
+      pass([&](int c) { return v[c]; }, 14 + 8 * ps, [&](int c, uint32_t pos) { s_v[pos] = v[c]; });
+#pragma unroll
+      for (int c = 0; c < kPL; c++) {
+        const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
+        if (i < end) v[c] = s_v[i];
+      }
+    }
+    // element v & 16383 of the input takes position i: gathered into
+    // (k1, i1), then copied back to (k0, i0)
+#pragma unroll
+    for (int c = 0; c < kPL; c++) {
+      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
+      if (i < end) {
+        const uint32_t src = (uint32_t)(v[c] & 16383u);
+        kb[i] = ka[src];
+        ib[i] = ia[src];
+      }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < m; i += kMT) { ka[i] = kb[i]; ia[i] = ib[i]; }
+    return;
+  }
+  // keys too wide to pack with the position: the elements are read where
+  // they are used (from L2: the segment's 192 KiB stay there)
+  for (uint32_t ps = 0; ps < passes; ps++) {
+    const auto at = [&](int c) { return beg + (uint32_t)c * kWave + lane_id(); };
+    pass([&](int c) { return ka[at(c)]; }, shift0 + 8 * ps, [&](int c, uint32_t pos) {
+      kb[pos] = ka[at(c)];
+      ib[pos] = ia[at(c)];
+    });
     uint64_t *tk = ka; ka = kb; kb = tk;
     uint32_t *ti = ia; ia = ib; ib = ti;
   }
