@@ -1118,13 +1118,13 @@ static int md_compress_impl(int nf, const float *const *fields, uint64_t n, doub
     for (int f = 0; f < nf; f++) szf.push_back(fields[f]);
     if (d_perm) SZNB_LAUNCH("md_iota", md_iota, dim3(grid), dim3(256), 0, s, d_perm, n);
   } else {
-    SZNB_LAUNCH("md_keys", md_keys, dim3(grid), dim3(256), 0, s, kf, ks, n, ctl, k0, i0);
+    SZNB_LAUNCH("md_keys", md_keys, dim3(grid), dim3(256), 0, s, kf, ks, n, ctl, k1, i1);
     // the sort's LDS-resident passes: 8 bytes per element of a segment
     const size_t sort_lds = 8ull * M.seg;
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(md_sort), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)sort_lds) != hipSuccess)
       return SZNB_EDEVICE;
-    SZNB_LAUNCH("md_sort", md_sort, dim3(nseg), dim3(1024), sort_lds, s, k0, i0, k1, i1, n, M.k, ctl);
+    SZNB_LAUNCH("md_sort", md_sort, dim3(nseg), dim3(1024), sort_lds, s, k1, i1, k0, i0, n, M.k, ctl);
     const int first = M.kind == 2 ? 3 : M.kind == 3 ? nf : 0;
     for (int f = first; f < nf; f++) {
       float *pfp = reinterpret_cast<float *>(ws + L.perm + L.perm_stride * f);

@@ -145,15 +145,16 @@ __device__ inline uint64_t md_lanemask_lt() {
   return l ? (~0ull >> (64 - l)) : 0ull;
 }
 
-// Stable sort of one segment's (key, idx) pairs by key >> (digit k), LSD on
-// 8-bit digits; each of the 16 waves owns a contiguous slice of the current
-// order and keeps it.  When the sorted bits and the 14-bit position in the
-// segment fit in 64 bits, every pass stays in LDS (dynamic, 8 bytes per
-// element): the packed values are scattered there and read back in the next
-// pass's order, and the keys and indices are gathered by position at the
-// end.  Otherwise each pass ping-pongs through (k0, i0) and (k1, i1).
-__global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint64_t *k1, uint32_t *i1, uint64_t n,
-                                               uint32_t k_ignored, const MdCtl *ctl) {
+// Stable sort of one segment's (key, idx) pairs from (kin, iin) into (kout,
+// iout) by key >> (digit k), LSD on 8-bit digits; each of the 16 waves owns a
+// contiguous slice of the current order and keeps it.  When the sorted bits
+// and the 14-bit position in the segment fit in 64 bits, every pass stays in
+// LDS (dynamic, 8 bytes per element): the packed values are scattered there
+// and read back in the next pass's order, and the keys and indices are
+// gathered by position at the end.  Otherwise each pass ping-pongs between
+// the two buffers (the input's are overwritten).
+__global__ __launch_bounds__(kMT) void md_sort(uint64_t *kin, uint32_t *iin, uint64_t *kout, uint32_t *iout,
+                                               uint64_t n, uint32_t k_ignored, const MdCtl *ctl) {
   extern __shared__ __align__(16) uint64_t s_v[];
   __shared__ uint32_t s_cnt[256 * kMW];
   __shared__ uint32_t s_tot[kMW];
@@ -166,8 +167,8 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
   const uint32_t shift0 = ctl->digit * k_ignored;
   const uint32_t bits = ctl->keybits > shift0 ? ctl->keybits - shift0 : 0;
   const uint32_t passes = (bits + 7) / 8;
-  uint64_t *ka = k0 + base, *kb = k1 + base;
-  uint32_t *ia = i0 + base, *ib = i1 + base;
+  uint64_t *ka = kin + base, *kb = kout + base;
+  uint32_t *ia = iin + base, *ib = iout + base;
   const uint32_t segw = (m + kMW - 1) / kMW;
   const uint32_t beg = min(m, segw * w), end = min(m, beg + segw);
   constexpr int kPL = kMdSegMax / kMT;  // chunks of 64 per wave
@@ -227,8 +228,7 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
         if (i < end) v[c] = s_v[i];
       }
     }
-    // element v & 16383 of the input takes position i: gathered into
-    // (k1, i1), then copied back to (k0, i0)
+    // element v & 16383 of the input takes position i
 #pragma unroll
     for (int c = 0; c < kPL; c++) {
       const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
@@ -238,8 +238,6 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
         ib[i] = ia[src];
       }
     }
-    __syncthreads();
-    for (uint32_t i = t; i < m; i += kMT) { ka[i] = kb[i]; ia[i] = ib[i]; }
     return;
   }
   // keys too wide to pack with the position: the elements are read where
@@ -253,8 +251,9 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *k0, uint32_t *i0, uint6
     uint64_t *tk = ka; ka = kb; kb = tk;
     uint32_t *ti = ia; ia = ib; ib = ti;
   }
-  // leave the result in (k0, i0)
-  if (passes & 1u) {
+  // the result to (kout, iout): after an even number of passes it is back
+  // in the input buffers
+  if (!(passes & 1u)) {
     for (uint32_t i = t; i < m; i += kMT) { kb[i] = ka[i]; ib[i] = ia[i]; }
   }
 }
