@@ -1238,7 +1238,7 @@ constexpr uint64_t kFlagAgg = 1ull << 62, kFlagPre = 2ull << 62, kValMask = (1ul
 constexpr int kEncWin = 2048;  // pack kernel: codewords held in LDS
 constexpr uint32_t kEncBase = 32768u - kEncWin / 2;
 template <int E>
-__global__ __launch_bounds__(kThreads, 5) void k_pack(const CField *__restrict__ F, int nf,
+__global__ __launch_bounds__(kThreads, 4) void k_pack(const CField *__restrict__ F, int nf,
                                                    const uint64_t *__restrict__ fb0, uint64_t total, GCtl *gc) {
   constexpr int S = E * kThreads;
   constexpr int CWMAX = S * kLMax / 32 + 16;  // code words plus the skip table
