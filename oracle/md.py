@@ -21,7 +21,7 @@ Readings where the paper is silent:
 * B = max over the three coordinates of bitlen(P_c) bits per coordinate, at
   most 21 (a 63-bit key); digit j of the key holds (x_j, y_j, z_j), x highest;
 * segments are index ranges of 16384 particles (Tables 4 and 5);
-* the coordinate stream also stores, for every 256 keys of a segment, the
+* the coordinate stream also stores, for every 64 keys of a segment, the
   bit offset where their code starts, so that a decoder can start at each
   of them (the entry for key 0 of the segment is 0);
 * velocity-based R-index (Sec. 5.3, Table 6): the same interleave built from
@@ -34,7 +34,7 @@ Readings where the paper is silent:
   velocity field's own lattice indices in R-index order, per segment the
   minimum raw (Bv = bit length of the field's lattice span), a Rice
   parameter chosen as for the keys, and every value minus the minimum
-  Rice-coded (escape to Bv raw bits); entry points every 256 values;
+  Rice-coded (escape to Bv raw bits); entry points every 64 values;
 * CPC2000's "adaptive variable-length encoding with status bits" (Sec. 2,
   Sec. 5.2) is read as Rice coding of the key deltas of each sorted segment:
   parameter r = argmin_r sum(floor(d / 2^r) + 1 + r) (ties to the smaller r),
@@ -53,7 +53,7 @@ import numpy as np
 from . import EB_REL, LV, compress, decompress, lattice, params, reconstruct_array
 
 SEG = 16384
-SUB = 256  # keys per decoder entry point
+SUB = 64  # keys per decoder entry point
 SPEED, TRADEOFF, COMPRESSION, CPC2000 = 0, 1, 2, 3
 KEY_COORD, KEY_VEL, KEY_ALL = 0, 1, 2
 PRX_IGNORED = 6  # Table 5: segment 16384, six ignored 3-bit digits

@@ -1232,13 +1232,13 @@ static int md_decompress_impl(const void *d_in, uint64_t in_len, int nf, uint64_
   rc = decompress_run(P, s);
   if (rc) return rc;
   const unsigned gmax = (unsigned)L.nseg_max;  // the smallest segment size's count: extra workgroups return
-  // relative keys and the bases of every 256 keys (n / 256 + 1 entries at most)
+  // relative keys and the bases of every 64 keys (n / 64 + 1 entries at most)
   uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys0), *kbase = reinterpret_cast<uint64_t *>(ws + L.keys1);
-  SZNB_LAUNCH("cpc_decode", cpc_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, n, keys, kbase, cstat);
+  SZNB_LAUNCH("cpc_decode", cpc_decode, dim3(gmax), dim3(kCpcThreads), 0, s, in, ctl, n, keys, kbase, cstat);
   SZNB_LAUNCH("cpc_coords", cpc_coords, dim3(dv->cus * 8), dim3(256), 0, s, in, ctl, n, keys, kbase, outs[0],
               outs[1], outs[2], cstat);
   for (int j = 0; j + 3 < nf; j++)
-    SZNB_LAUNCH("cpv_decode", cpv_decode, dim3(gmax), dim3(kWave), 0, s, in, ctl, j, n, outs[3 + j], cstat);
+    SZNB_LAUNCH("cpv_decode", cpv_decode, dim3(gmax), dim3(kCpcThreads), 0, s, in, ctl, j, n, outs[3 + j], cstat);
   MdStatus ss{};
   int nss = 0;
   ss.s[nss++] = cstat;

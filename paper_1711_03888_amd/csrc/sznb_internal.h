@@ -201,7 +201,8 @@ constexpr uint32_t kLutInvalid = 1u << 23;
 // ------------------------------------------------------------ MD modes
 
 constexpr uint32_t kMdSegMax = 16384;  // largest reorder / CPC segment
-constexpr uint32_t kMdSub = 256;       // values per CPC decoder entry point
+constexpr uint32_t kMdSub = 64;        // values per CPC decoder entry point
+constexpr int kCpcThreads = (int)(kMdSegMax / kMdSub);  // CPC decoders: one thread per entry point of a segment
 constexpr uint32_t kMdHdr = 96;        // container header bytes
 constexpr uint32_t kCpHdr = 104;       // CPC coordinate stream header bytes
 constexpr uint32_t kCvHdr = 56;        // CPC velocity stream header bytes

@@ -23,8 +23,8 @@
 //               (velocities), Rice parameter, coded size
 //   cpc_offsets segment word offsets, stream header
 //   cpc_pack    per segment: first key or minimum, parameter, Rice codes
-//   cpc_decode  one wave per segment, one lane per 256 keys (entry points
-//               stored in the stream): keys back
+//   cpc_decode  one workgroup per segment, one thread per 64 keys (entry
+//               points stored in the stream): keys back
 //   cpc_coords  keys -> coordinates
 //   cpv_decode  the same for a velocity stream (one pass: no prefix sums)
 //   md_assemble container header and sub-stream copies
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n
   }
 }
 
-// entry points of all segments (one per 256 values)
+// entry points of all segments (one per 64 values)
 __host__ __device__ inline uint64_t cpc_entries(uint64_t n, uint32_t seg) {
   const uint64_t nseg = (n + seg - 1) / seg;
   return nseg ? (nseg - 1) * (seg / kMdSub) + (n - (nseg - 1) * seg + kMdSub - 1) / kMdSub : 0;
@@ -370,7 +370,7 @@ __device__ inline void put64(uint8_t *p, uint64_t o, uint64_t v) {
 }
 
 // Stream headers, then u32 seg_bits[nseg] (padded to 8 bytes), then the
-// entry points (for every segment and every 256 values of it, u32 bit offset
+// entry points (for every segment and every 64 values of it, u32 bit offset
 // from the segment start of that value's code; padded to 8 bytes), then the
 // segments' words.
 // Coordinates (104 bytes): "SZCP" u16 2 u8 B u8 0 u64 n u32 nseg u32 seg
@@ -622,19 +622,20 @@ struct SegReader {
   }
 };
 
-// stages a segment's words in LDS (coalesced, sixteen loads per lane in
-// flight before they are stored)
-__device__ inline void stage_words(uint32_t *s_seg, gptr<const uint32_t> gw, uint64_t nw, uint32_t lane) {
-  for (uint32_t i0 = 0; i0 < nw; i0 += 16u * kWave) {
-    uint32_t a[16];
+// stages a segment's words in LDS (coalesced over the workgroup, four loads
+// per thread in flight before they are stored)
+__device__ inline void stage_words(uint32_t *s_seg, gptr<const uint32_t> gw, uint64_t nw) {
+  const uint32_t t = threadIdx.x, nt = blockDim.x;
+  for (uint32_t i0 = 0; i0 < nw; i0 += 4u * nt) {
+    uint32_t a[4];
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-      const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + (uint32_t)u * nt + t;
       a[u] = i < nw ? gw[i] : 0u;
     }
 #pragma unroll
-    for (int u = 0; u < 16; u++) {
-      const uint32_t i = i0 + (uint32_t)u * kWave + lane;
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + (uint32_t)u * nt + t;
       if (i < nw) s_seg[i] = a[u];
     }
   }
@@ -642,21 +643,24 @@ __device__ inline void stage_words(uint32_t *s_seg, gptr<const uint32_t> gw, uin
 
 __device__ inline bool seg_size_ok(uint32_t S) { return S >= 1024u && S <= kMdSegMax && !(S & (S - 1)); }
 
-// One wave per segment, one lane per 256 keys: each lane starts at its entry
-// point and writes the running sums of its deltas to kout; the wave scans the
-// lanes' totals into kbase (one entry per 256 keys: key i is kout[i] +
-// kbase[i / 256]).  Every read is checked
-// against the segment's bit count and the stream length, and every lane must
-// end exactly at the next lane's entry point; a stream that fails a check
-// sets ECORRUPT.  The stream is sub-stream 0 of the container (offset and
-// length from md_parse); the grid covers the smallest segment size.
-__global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdCtl *ctl, uint64_t n, uint64_t *kout,
-                                                    uint64_t *kbase, int *status) {
+// One workgroup per segment, one thread per 64 keys (kCpcThreads threads):
+// each thread starts at its entry point and writes the running sums of its
+// deltas to kout; the workgroup scans the threads' totals into kbase (one
+// entry per 64 keys: key i is kout[i] + kbase[i / 64]).  Every read is
+// checked against the segment's bit count and the stream length, and every
+// thread must end exactly at the next thread's entry point; a stream that
+// fails a check sets ECORRUPT.  The stream is sub-stream 0 of the container
+// (offset and length from md_parse); the grid covers the smallest segment
+// size.
+__global__ __launch_bounds__(kCpcThreads) void cpc_decode(const uint8_t *in, const MdCtl *ctl, uint64_t n,
+                                                          uint64_t *kout, uint64_t *kbase, int *status) {
+  __shared__ uint32_t s_seg[kCpcLdsWords];
+  __shared__ unsigned long long s_wtot[kCpcThreads / kWave];
   if (ctl->status || ctl->kind < 2) return;
   const uint8_t *cs = in + ctl->sub_off[0];
   const uint64_t cs_len = ctl->sub_len[0];
-  const uint32_t seg = blockIdx.x, lane = threadIdx.x;
-  if (cs_len < kCpHdr) { if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
+  const uint32_t seg = blockIdx.x, t = threadIdx.x, w = t / kWave;
+  if (cs_len < kCpHdr) { if (seg == 0 && t == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
   const uint32_t nseg = *reinterpret_cast<const uint32_t *>(cs + 16);
   const uint32_t S = *reinterpret_cast<const uint32_t *>(cs + 20);
   const uint32_t kb = *reinterpret_cast<const uint32_t *>(cs + 24);
@@ -665,15 +669,15 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
   if (*reinterpret_cast<const uint32_t *>(cs) != 0x50435A53u || (*reinterpret_cast<const uint32_t *>(cs + 4) & 0xffffu) != 2u ||
       nhdr != n || !seg_size_ok(S) || S != ctl->seg || nseg != (n + S - 1) / S || kb > 63 || kb == 0 ||
       kCpHdr + align8(4ull * nseg) + align8(4ull * cpc_entries(n, S)) > cs_len) {
-    if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    if (seg == 0 && t == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
     return;
   }
   const uint64_t etab = kCpHdr + align8(4ull * nseg);
   const uint64_t tab = etab + align8(4ull * cpc_entries(n, S));
   if (seg >= nseg) return;
   const gptr<const uint32_t> sb = G(reinterpret_cast<const uint32_t *>(cs + kCpHdr));
-  uint64_t woff = 0;
-  for (uint32_t s = lane; s < seg; s += kWave) woff += (sb[s] + 31) / 32;
+  uint64_t woff = 0;  // every wave sums the earlier segments' words
+  for (uint32_t s2 = lane_id(); s2 < seg; s2 += kWave) woff += (sb[s2] + 31) / 32;
   woff = wave_sum(woff);
   const uint64_t nbits = sb[seg];
   const uint64_t avail = (cs_len - tab) / 4;
@@ -682,16 +686,15 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
   const gptr<const uint32_t> ent = G(reinterpret_cast<const uint32_t *>(cs + etab)) + (uint64_t)seg * (S / kMdSub);
   const uint64_t base = (uint64_t)seg * S;
   const uint32_t m = (uint32_t)min((uint64_t)S, n - base);
-  const uint32_t k0 = lane * kMdSub, k1 = min(m, k0 + kMdSub);  // this lane's keys
+  const uint32_t k0 = t * kMdSub, k1 = min(m, k0 + kMdSub);  // this thread's keys
   const bool active = k0 < m;
   const uint64_t nw = (nbits + 31) / 32;
-  __shared__ uint32_t s_seg[kCpcLdsWords];
   const bool in_lds = !bad && nw <= kCpcLdsWords;
-  if (in_lds) stage_words(s_seg, gw, nw, lane);
+  if (in_lds) stage_words(s_seg, gw, nw);
   __syncthreads();
   // The bit reader refills from LDS or from global memory, decided once per
   // segment: a refill that could take either path made the compiler wait
-  // for every vector-memory operation in flight (pass 2's stores) at each
+  // for every vector-memory operation in flight (the key stores) at each
   // refill.
   const auto run = [&](auto lds) {
     constexpr bool kL = decltype(lds)::value;
@@ -703,20 +706,17 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
       r = (uint32_t)R.take(6);
       if (r > kb) bad = true;
     }
-    const uint64_t start = active ? ent[lane] : 0;
-    const uint64_t stop = (k1 < m) ? ent[lane + 1] : nbits;
-    if (active && (start > stop || stop > nbits || (lane == 0 && start != 0))) bad = true;
+    const uint64_t start = active ? ent[t] : 0;
+    const uint64_t stop = (k1 < m) ? ent[t + 1] : nbits;
+    if (active && (start > stop || stop > nbits || (t == 0 && start != 0))) bad = true;
     // the segment's first key is stored raw (before the Rice parameter)
     const auto first = [&]() -> uint64_t {
       const uint64_t k = R.take_wide(kb);
       (void)R.take(6);
       return k;
     };
-    // one pass: each lane writes its keys relative to its first key's
-    // predecessor (the running sum of its deltas) and its total; the wave's
-    // exclusive scan of the totals gives every lane's base, which cpc_coords
-    // adds back (global stores: flat stores in flight would hold up every
-    // LDS refill of the bit reader)
+    // one pass: the running sums of the deltas (global stores: flat stores
+    // in flight would hold up every LDS refill of the bit reader)
     uint64_t sum = 0;
     if (active && !bad) {
       R.seek(start);
@@ -728,21 +728,21 @@ __global__ __launch_bounds__(kWave) void cpc_decode(const uint8_t *in, const MdC
       });
       if (R.pos != stop) bad = true;
     }
-    uint64_t inc = sum;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint64_t o = __shfl_up(inc, d, kWave);
-      if ((int)lane >= d) inc += o;
-    }
-    if (__ballot(bad) != 0) {
-      if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    // exclusive scan of the threads' totals over the workgroup
+    const unsigned long long inc = wave_incl_scan((unsigned long long)sum);
+    if (lane_id() == kWave - 1) s_wtot[w] = inc;
+    if (__syncthreads_or(bad)) {
+      if (t == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
       return;
     }
-    if (active) G(kbase)[base / kMdSub + lane] = inc - sum;
+    uint64_t pre = inc - sum;
+    for (uint32_t j = 0; j < w; j++) pre += s_wtot[j];
+    if (active) G(kbase)[base / kMdSub + t] = pre;
   };
   if (in_lds) run(std::true_type{}); else run(std::false_type{});
 }
 
-// The decoded keys back to coordinates (key i = kout[i] + kbase[i / 256]),
+// The decoded keys back to coordinates (key i = kout[i] + kbase[i / 64]),
 // x~ = fl32(fma(p, step, mn)) of each coordinate's lattice index (the bits of the key at its place in every
 // 3-bit digit), after cpc_decode, over the whole grid.  Nothing is written
 // for a container that failed a check.
@@ -768,16 +768,17 @@ __global__ void cpc_coords(const uint8_t *in, const MdCtl *ctl, uint64_t n, cons
   }
 }
 
-// CPC2000 velocity stream (sub-stream 1 + j of the container): one wave per
-// segment, one lane per 256 values, one pass (each value is the minimum plus
-// its code; no prefix).  The same checks as the key decoder.
-__global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdCtl *ctl, int j, uint64_t n,
-                                                    float *out, int *status) {
+// CPC2000 velocity stream (sub-stream 1 + j of the container): one
+// workgroup per segment, one thread per 64 values, one pass (each value is
+// the minimum plus its code; no prefix).  The same checks as the key decoder.
+__global__ __launch_bounds__(kCpcThreads) void cpv_decode(const uint8_t *in, const MdCtl *ctl, int j, uint64_t n,
+                                                          float *out, int *status) {
+  __shared__ uint32_t s_seg[kCpcLdsWords];
   if (ctl->status || ctl->kind != 3) return;
   const uint8_t *cs = in + ctl->sub_off[1 + j];
   const uint64_t cs_len = ctl->sub_len[1 + j];
-  const uint32_t seg = blockIdx.x, lane = threadIdx.x;
-  if (cs_len < kCvHdr) { if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
+  const uint32_t seg = blockIdx.x, t = threadIdx.x;
+  if (cs_len < kCvHdr) { if (seg == 0 && t == 0) atomicCAS(status, 0, SZNB_ECORRUPT); return; }
   const uint32_t nseg = *reinterpret_cast<const uint32_t *>(cs + 16);
   const uint32_t S = *reinterpret_cast<const uint32_t *>(cs + 20);
   const uint32_t vb = *reinterpret_cast<const uint32_t *>(cs + 24);
@@ -787,7 +788,7 @@ __global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdC
   if (*reinterpret_cast<const uint32_t *>(cs) != 0x56435A53u || (h1 & 0xffffu) != 1u || (h1 >> 16) != vb ||
       nhdr != n || !seg_size_ok(S) || S != ctl->seg || nseg != (n + S - 1) / S || vb > 31 || vb == 0 ||
       kCvHdr + align8(4ull * nseg) + align8(4ull * cpc_entries(n, S)) > cs_len) {
-    if (seg == 0 && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    if (seg == 0 && t == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
     return;
   }
   if (seg >= nseg) return;
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdC
                                                        ((uint64_t)*reinterpret_cast<const uint32_t *>(cs + 48) << 32)));
   const gptr<const uint32_t> sb = G(reinterpret_cast<const uint32_t *>(cs + kCvHdr));
   uint64_t woff = 0;
-  for (uint32_t s = lane; s < seg; s += kWave) woff += (sb[s] + 31) / 32;
+  for (uint32_t s2 = lane_id(); s2 < seg; s2 += kWave) woff += (sb[s2] + 31) / 32;
   woff = wave_sum(woff);
   const uint64_t nbits = sb[seg];
   bool bad = woff + (nbits + 31) / 32 > (cs_len - tab) / 4;
@@ -806,12 +807,11 @@ __global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdC
   const gptr<const uint32_t> ent = G(reinterpret_cast<const uint32_t *>(cs + etab)) + (uint64_t)seg * (S / kMdSub);
   const uint64_t base = (uint64_t)seg * S;
   const uint32_t m = (uint32_t)min((uint64_t)S, n - base);
-  const uint32_t v0 = lane * kMdSub, v1 = min(m, v0 + kMdSub);
+  const uint32_t v0 = t * kMdSub, v1 = min(m, v0 + kMdSub);
   const bool active = v0 < m;
   const uint64_t nw = (nbits + 31) / 32;
-  __shared__ uint32_t s_seg[kCpcLdsWords];
   const bool in_lds = !bad && nw <= kCpcLdsWords;
-  if (in_lds) stage_words(s_seg, gw, nw, lane);
+  if (in_lds) stage_words(s_seg, gw, nw);
   __syncthreads();
   const auto run = [&](auto lds) {
     constexpr bool kL = decltype(lds)::value;
@@ -824,21 +824,22 @@ __global__ __launch_bounds__(kWave) void cpv_decode(const uint8_t *in, const MdC
       r = (uint32_t)R.take(6);
       if (r > vb) bad = true;
     }
-    const uint64_t start = active ? ent[lane] : 0;
-    const uint64_t stop = (v1 < m) ? ent[lane + 1] : nbits;
-    if (active && (start > stop || stop > nbits || (lane == 0 && start != vb + 6u))) bad = true;
-    if (__ballot(bad)) {
-      if (lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    const uint64_t start = active ? ent[t] : 0;
+    const uint64_t stop = (v1 < m) ? ent[t + 1] : nbits;
+    if (active && (start > stop || stop > nbits || (t == 0 && start != vb + 6u))) bad = true;
+    if (__syncthreads_or(bad)) {
+      if (t == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
       return;
     }
-    if (!active) return;
-    R.seek(start);
-    gptr<float> go = G(out) + base + v0;
-    R.codes(v0, v1, r, vb, [&](uint64_t v) {
-      *go++ = (float)fma((double)(int32_t)(uint32_t)(vmin + v), step, (double)mn);
-    });
-    if (R.pos != stop) bad = true;
-    if (__ballot(bad) && lane == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
+    if (active) {
+      R.seek(start);
+      gptr<float> go = G(out) + base + v0;
+      R.codes(v0, v1, r, vb, [&](uint64_t v) {
+        *go++ = (float)fma((double)(int32_t)(uint32_t)(vmin + v), step, (double)mn);
+      });
+      if (R.pos != stop) bad = true;
+    }
+    if (__syncthreads_or(bad) && t == 0) atomicCAS(status, 0, SZNB_ECORRUPT);
   };
   if (in_lds) run(std::true_type{}); else run(std::false_type{});
 }

@@ -183,7 +183,7 @@ def test_container_layout():
 
 
 def test_cpc_entry_points_start_codes():
-    # every stored entry point is where the code of key 256 c begins: an
+    # every stored entry point is where the code of key SUB c begins: an
     # independent bit reader started there decodes the right delta
     rng = np.random.default_rng(12)
     keys = np.cumsum(rng.geometric(1 / 3000.0, size=1000)).astype(np.uint64)
@@ -191,7 +191,7 @@ def test_cpc_entry_points_start_codes():
     words, nbits, ent = md.cpc_encode_segment(keys, kb, with_entries=True)
     bits = "".join(format(int(w), "032b") for w in words)[:nbits]
     r = int(bits[kb:kb + 6], 2)
-    assert list(ent[:1]) == [0] and len(ent) == 4
+    assert list(ent[:1]) == [0] and len(ent) == -(-1000 // md.SUB)
     for c in range(1, len(ent)):
         p = int(ent[c])
         q = 0
@@ -202,7 +202,7 @@ def test_cpc_entry_points_start_codes():
             d = int(bits[p:p + kb], 2)
         else:
             d = (q << r) | (int(bits[p + 1:p + 1 + r], 2) if r else 0)
-        assert d == int(keys[256 * c] - keys[256 * c - 1])
+        assert d == int(keys[md.SUB * c] - keys[md.SUB * c - 1])
 
 
 # ---- velocity keys, six-field keys, segment sizes and CPC2000 velocities
@@ -281,7 +281,7 @@ def test_cpv_escape_and_entries():
             q += 1
             p += 1
         d = int(bits[p:p + 21], 2) if q == md.CPC_ESC_Q else (q << r) | (int(bits[p + 1:p + 1 + r], 2) if r else 0)
-        assert mn + d == int(vals[256 * c])
+        assert mn + d == int(vals[md.SUB * c])
 
 
 @pytest.mark.parametrize("m", [md.CPC2000, md.mode(md.TRADEOFF, 12, 0, md.KEY_VEL),
