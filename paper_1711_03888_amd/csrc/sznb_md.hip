@@ -294,8 +294,9 @@ template <bool kOffset>
 __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n, const MdCtl *ctl,
                                                  const uint32_t *vbp, uint32_t *seg_r, uint32_t *seg_bits,
                                                  uint64_t *seg_min) {
-  __shared__ unsigned long long s_sum[kMW];
-  __shared__ uint32_t s_cost[64 * kMW];
+  __shared__ unsigned long long s_sum[kMW], s_best;
+  __shared__ uint32_t s_cost[64 * kMW], s_num[kMW];
+  __shared__ bool s_ok;
   if (ctl->status) return;
   const uint32_t seg = blockIdx.x, S = ctl->seg;
   const uint64_t base = (uint64_t)seg * S;
@@ -331,29 +332,75 @@ __global__ __launch_bounds__(kMT) void cpc_count(const uint64_t *val, uint64_t n
       dl[j] = i < m ? val[base + i] - val[base + i - 1] : 0u;
     }
   }
-  // every wave's cost for every parameter, then one reduction: lane r of
-  // wave 0 totals parameter r, and the wave's minimum of (cost, r) picks the
-  // cheapest, the smaller r on a tie
-  for (uint32_t r = 0; r <= vb; r++) {
+  const auto coded = [&](int j) { return first + t + (uint32_t)j * kMT < m; };
+  // the parameters' costs C(r) (sums of rice_cost) for r in [lo, lo + nr),
+  // each wave's into s_cost[(r - lo) * kMW + w]
+  const auto costs = [&](uint32_t lo, uint32_t nr) {
+    for (uint32_t r = lo; r < lo + nr; r++) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; j++)
+        if (coded(j)) c += (uint32_t)rice_cost(dl[j], r, vb);
+      c = wave_sum(c);
+      if (lane_id() == 0) s_cost[(r - lo) * kMW + w] = c;
+    }
+  };
+  // wave 0: the smallest (C(r), r) of the nr parameters from lo, as C << 6 | r
+  const auto best_of = [&](uint32_t lo, uint32_t nr) {
+    const uint32_t i = lane_id();
+    uint64_t tot = 0;
+    if (i < nr)
+      for (int j = 0; j < kMW; j++) tot += s_cost[i * kMW + j];
+    return wave_min_u64(i < nr ? (tot << 6) | (lo + i) : ~0ull);
+  };
+  // Eight parameters around the codes' mean bit length, then proof that
+  // no other parameter does better: every code costs at least 1 + r bits, so
+  // for r above the window C(r) >= (number of codes)(1 + r); below the
+  // window a code costs at least min(32 + vb, (d >> (lo - 1)) + 1) bits.
+  // Without the proof every parameter is costed.  Either way the cheapest
+  // parameter is taken, the smaller on a tie.
+  uint64_t su = 0;
+  uint32_t cn = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; j++)
+    if (coded(j)) { su += bitlen64(dl[j]); cn++; }
+  su = wave_sum(su);
+  cn = wave_sum(cn);
+  if (lane_id() == 0) { s_sum[w] = su; s_num[w] = cn; }
+  __syncthreads();
+  uint64_t sum_all = 0, num_all = 0;
+  for (int j = 0; j < kMW; j++) { sum_all += s_sum[j]; num_all += s_num[j]; }
+  const uint32_t mb = (uint32_t)(num_all ? sum_all / num_all : 0ull);
+  const uint32_t lo = min(mb > 4u ? mb - 4u : 0u, vb), nr = min(vb - lo + 1u, 8u);
+  costs(lo, nr);
+  if (lo > 0) {
     uint32_t c = 0;
 #pragma unroll
     for (int j = 0; j < kPer; j++)
-      if (first + t + (uint32_t)j * kMT < m) c += (uint32_t)rice_cost(dl[j], r, vb);
+      if (coded(j)) c += (uint32_t)min((uint64_t)kEscQ + vb, (dl[j] >> (lo - 1)) + 1u);
     c = wave_sum(c);
-    if (lane_id() == 0) s_cost[r * kMW + w] = c;
+    if (lane_id() == 0) s_cost[8 * kMW + w] = c;
   }
   __syncthreads();
   if (w == 0) {
-    const uint32_t r = lane_id();
-    uint64_t tot = 0;
-    if (r <= vb)
-      for (int j = 0; j < kMW; j++) tot += s_cost[r * kMW + j];
-    const uint64_t best = wave_min_u64(r <= vb ? (tot << 6) | r : ~0ull);
-    if (r == 0) {
-      seg_r[seg] = (uint32_t)(best & 63u);
-      seg_bits[seg] = (uint32_t)(vb + 6 + (m > first ? (best >> 6) : 0ull));
-      if (kOffset) seg_min[seg] = vmin;
-    }
+    const uint64_t best = best_of(lo, nr);
+    uint64_t low = 0;
+    for (int j = 0; j < kMW; j++) low += s_cost[8 * kMW + j];
+    const bool ok_hi = lo + nr > vb || num_all * (2u + (lo + nr - 1u)) >= (best >> 6);
+    const bool ok_lo = lo == 0 || low > (best >> 6);
+    if (lane_id() == 0) { s_best = best; s_ok = ok_hi && ok_lo; }
+  }
+  __syncthreads();
+  uint64_t best = s_best;
+  if (!s_ok) {
+    costs(0, vb + 1);
+    __syncthreads();
+    if (w == 0) best = best_of(0, vb + 1);
+  }
+  if (t == 0) {
+    seg_r[seg] = (uint32_t)(best & 63u);
+    seg_bits[seg] = (uint32_t)(vb + 6 + (m > first ? (best >> 6) : 0ull));
+    if (kOffset) seg_min[seg] = vmin;
   }
 }
 
@@ -497,9 +544,20 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *val, uint64_t n,
   // thread t codes values i in [lo, hi); bit offsets by a workgroup scan
   const uint32_t per = (m + kMT - 1) / kMT;
   const uint32_t lo = min(m, t * per), hi = min(m, lo + per);
+  // this thread's coded quantities, read once (at most kMdSegMax / kMT)
+  constexpr int kPer = kMdSegMax / kMT;
+  uint64_t cq[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t i = lo + (uint32_t)j;
+    cq[j] = i < hi && (kOffset || i > 0) ? code_of(i) : 0ull;
+  }
   unsigned long long mine = 0;
-  for (uint32_t i = lo; i < hi; i++)
-    if (kOffset || i > 0) mine += rice_cost(code_of(i), r, vb);
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const uint32_t i = lo + (uint32_t)j;
+    if (i < hi && (kOffset || i > 0)) mine += rice_cost(cq[j], r, vb);
+  }
   if (lo == 0 && hi > 0) mine += vb + 6;
   const unsigned long long inc = wave_incl_scan(mine);
   if (lane_id() == kWave - 1) s_tot[w] = inc;
@@ -514,7 +572,10 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *val, uint64_t n,
     b.acc = 0;
     b.first_word = pre >> 5;
     b.last_word = (pre + mine - 1) >> 5;
-    for (uint32_t i = lo; i < hi; i++) {
+#pragma unroll
+    for (int j = 0; j < kPer; j++) {
+      const uint32_t i = lo + (uint32_t)j;
+      if (i >= hi) break;
       if (i == 0) {
         if (!kOffset) ent[0] = 0u;  // a key segment starts with its first key raw
         wb_put_wide(b, kOffset ? vmin : val[base], vb);
@@ -522,7 +583,7 @@ __global__ __launch_bounds__(kMT) void cpc_pack(const uint64_t *val, uint64_t n,
         if (!kOffset) continue;
       }
       if ((i & (kMdSub - 1)) == 0) ent[i / kMdSub] = (uint32_t)(b.pos + b.na);
-      wb_rice(b, code_of(i), r, vb);
+      wb_rice(b, cq[j], r, vb);
     }
     if (b.na) wb_flush_word(b, b.pos >> 5, (uint32_t)(b.acc >> 32));
   }
