@@ -199,11 +199,20 @@ static int upload(const std::vector<Upload> &ups, hipStream_t s, bool may_stage)
       const int slot = g.next;
       g.next = (g.next + 1) % kStageSlots;
       if (g.used[slot] && hipEventSynchronize(g.ev[slot]) != hipSuccess) return SZNB_EDEVICE;
-      uint8_t *p = g.buf + (size_t)slot * kStageSlotBytes;
+      uint8_t *p0 = g.buf + (size_t)slot * kStageSlotBytes, *p = p0;
+      // destinations laid out as the slot packs them take one copy
+      bool packed = true;
+      for (size_t i = 0; i + 1 < ups.size(); i++)
+        packed = packed && static_cast<uint8_t *>(ups[i + 1].dst) == static_cast<uint8_t *>(ups[i].dst) +
+                                                                       al256(ups[i].bytes);
       for (const Upload &u : ups) {
         std::memcpy(p, u.src, u.bytes);
-        if (hipMemcpyAsync(u.dst, p, u.bytes, hipMemcpyHostToDevice, s) != hipSuccess) return SZNB_EDEVICE;
+        if (!packed && hipMemcpyAsync(u.dst, p, u.bytes, hipMemcpyHostToDevice, s) != hipSuccess) return SZNB_EDEVICE;
         p += al256(u.bytes);
+      }
+      if (packed && !ups.empty()) {
+        const size_t span = (size_t)(p - p0) - al256(ups.back().bytes) + ups.back().bytes;
+        if (hipMemcpyAsync(ups[0].dst, p0, span, hipMemcpyHostToDevice, s) != hipSuccess) return SZNB_EDEVICE;
       }
       if (hipEventRecord(g.ev[slot], s) != hipSuccess) return SZNB_EDEVICE;
       g.used[slot] = true;
@@ -243,10 +252,6 @@ struct CLayout {
 static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) {
   CLayout L;
   uint64_t o = 0;
-  L.gctl = o; o = al256(o + sizeof(GCtl));
-  L.states = o; o = al256(o + kStateStride * nf);
-  L.fields = o; o = al256(o + sizeof(CField) * nf);
-  L.fb0 = o; o = al256(o + 8ull * (nf + 1));
   L.total_blocks = 0;
   L.nblocks.resize(nf); L.gblock0.resize(nf); L.nhist.resize(nf);
   int npairs = 0;
@@ -258,6 +263,17 @@ static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) 
     L.nhist[f] = (mode[f] & 3u) >= 2 ? 3 : 1;
     npairs += (int)L.nhist[f];
   }
+  // quantization plan: per workgroup its first visit and first field, per
+  // field its first and last workgroup; one histogram slab per visit
+  L.qslots = 1;
+  for (int f = 0; f < nf; f++) L.qslots = std::max<uint32_t>(L.qslots, (uint32_t)L.nhist[f]);
+  L.qmax = std::max<uint64_t>(1, std::min<uint64_t>(kMaxQuantWG, L.total_blocks));
+  L.gctl = o; o = al256(o + sizeof(GCtl));
+  L.states = o; o = al256(o + kStateStride * nf);
+  // the host-built descriptors back to back (one copy uploads them)
+  L.fields = o; o = al256(o + sizeof(CField) * nf);
+  L.fb0 = o; o = al256(o + 8ull * (nf + 1));
+  L.qmeta = o; o = al256(o + 4ull * (2 * L.qmax + 1 + 2ull * nf));
   L.blkstat = o; o = al256(o + 12ull * L.total_blocks);
   L.lbflag = o; o = al256(o + 8ull * L.total_blocks);
   L.hist.resize(nf); L.enc.resize(nf); L.book.resize(nf);
@@ -271,12 +287,6 @@ static CLayout compress_layout(int nf, const uint64_t *n, const uint32_t *mode) 
   L.hvar = 3 * nf <= kHuffSlots / 2 ? std::min(4, kHuffSlots / (3 * nf)) : 1;
   L.nslots = L.hvar > 1 ? 3 * nf * L.hvar : std::min(std::max(npairs, 1), kHuffSlots);
   L.hscratch = o; o = al256(o + hscratch_bytes_host() * (uint64_t)L.nslots);
-  // quantization plan: per workgroup its first visit and first field, per
-  // field its first and last workgroup; one histogram slab per visit
-  L.qslots = 1;
-  for (int f = 0; f < nf; f++) L.qslots = std::max<uint32_t>(L.qslots, (uint32_t)L.nhist[f]);
-  L.qmax = std::max<uint64_t>(1, std::min<uint64_t>(kMaxQuantWG, L.total_blocks));
-  L.qmeta = o; o = al256(o + 4ull * (2 * L.qmax + 1 + 2ull * nf));
   L.slabs = o; o = al256(o + 4ull * kWinWords * (L.qmax + (uint64_t)nf));
   L.total = o;
   return L;
@@ -484,9 +494,9 @@ static int compress_prepare(int nf, const float *const *fields, const uint64_t *
   const uint32_t gq = quant_grid((int)((1u << s0) / kThreads), learned, L, dv->cus);
   std::vector<uint32_t> qmeta;
   quant_plan(L, nf, gq, qmeta);
-  rc = upload({{ws + L.qmeta, qmeta.data(), 4 * qmeta.size()},
-               {ws + L.fields, hf.data(), sizeof(CField) * nf},
-               {ws + L.fb0, fb0.data(), 8ull * (nf + 1)}},
+  rc = upload({{ws + L.fields, hf.data(), sizeof(CField) * nf},
+               {ws + L.fb0, fb0.data(), 8ull * (nf + 1)},
+               {ws + L.qmeta, qmeta.data(), 4 * qmeta.size()}},
               stream, true);
   if (rc) return rc;
   P.cus = dv->cus;
