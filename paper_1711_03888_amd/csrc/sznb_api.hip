@@ -429,7 +429,9 @@ static int compress_run(const Launch &P, hipStream_t s, DevInfo *dv, bool params
   SZNB_LAUNCH("k_huff", k_huff, dim3(P.L.nslots), dim3(1024), 0, s, F, P.nf, P.ws + P.L.hscratch, hscratch_bytes_host(),
               (uint32_t)P.L.hvar, gc);
   SZNB_LAUNCH("k_books", k_books, dim3(P.nf), dim3(kThreads), 0, s, F);
-  if (tb) launch_E(false, P, s, gper);
+  // the pack kernel takes its blocks by ticket: one resident generation of
+  // workgroups (four per CU) so that none pays its start-up twice
+  if (tb) launch_E(false, P, s, (int)std::min<uint64_t>((uint64_t)dv->cus * 4, std::max<uint64_t>(tb, 1)));
   SZNB_LAUNCH("k_final", k_final, dim3((P.nf + 63) / 64), dim3(64), 0, s, F, P.nf);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
