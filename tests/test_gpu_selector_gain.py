@@ -2,10 +2,11 @@
 
 * nbody selector (trained on random-walk and cosmology blocks, where the
   exhaustive trial picks LV everywhere): same ratio as the exhaustive trial
-  within 1 %.  Its quantization kernel time is reported beside the trial's:
-  the trial costs about nine instructions per value and predictor, less than
-  the selector's features and network, so skipping it no longer pays; the
-  bound below only guards against a gross slowdown.
+  within 1 %, and its quantization kernel no more than 15 % slower than the
+  trial's (6 % on this test's 2^22-value fields).  The target of a faster compression is not met: the trial costs
+  about nine instructions per value and predictor, as much as the
+  selector's features and network (both kernels take 0.87-0.88 ms on the
+  2^26 x 6 snapshot, against 0.47 ms with no selection at all).
 * md selector (trained on FCC coordinate blocks, where LCF wins about a
   quarter of the blocks): ratio within 1 % of the exhaustive trial and above
   the fixed LV predictor, the method without a selector.
@@ -53,15 +54,15 @@ def test_nbody_selector_gain():
     snap = datagen.cosmology(1 << 22, seed=2)
     fields = list(snap.values())
     eb = 1e-4
-    sb, _, q_b = _compress(fields, eb, sznb.PRED_BESTFIT | sznb.EB_REL, reps=3)
-    sl, cl, q_l = _compress(fields, eb, sznb.PRED_LEARNED | sznb.EB_REL, reps=3)
+    sb, _, q_b = _compress(fields, eb, sznb.PRED_BESTFIT | sznb.EB_REL, reps=5)
+    sl, cl, q_l = _compress(fields, eb, sznb.PRED_LEARNED | sznb.EB_REL, reps=5)
     rb = sum(4 * f.size for f in fields) / sum(s.numel() for s in sb)
     rl = sum(4 * f.size for f in fields) / sum(s.numel() for s in sl)
     fb = sum(sznb.compress_fallbacks(cl.ws, len(fields)))
     print("ratio exhaustive %.4f learned %.4f; k_quant %.3f ms -> %.3f ms; fallbacks %d"
           % (rb, rl, q_b, q_l, fb), flush=True)
     assert rl >= 0.99 * rb
-    assert q_l < 2.0 * q_b
+    assert q_l < 1.15 * q_b
     # the first field decodes to the oracle's floats with the same choices
     ref = oracle.compress(fields[0], eb, sznb.PRED_LEARNED | sznb.EB_REL, selector=(params, tau))
     assert bytes(sl[0].cpu().numpy()) == ref
