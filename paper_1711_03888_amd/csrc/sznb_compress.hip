@@ -741,7 +741,8 @@ __global__ __launch_bounds__(kThreads) void k_features(const CField *__restrict_
 
 constexpr int kHT = 1024;
 constexpr int kHW = kHT / kWave;
-constexpr int kStage = 8192;  // largest merge batch ordered in LDS
+constexpr int kStage = 6144;  // largest merge batch ordered in LDS (and leaf sort in LDS)
+constexpr int kHLds = 8192;   // merge queues (sorted leaves, merged nodes) in LDS up to this many leaves
 
 struct HScratch {
   uint16_t *a_sym; uint32_t *a_f;        // present symbols in symbol order
@@ -870,6 +871,9 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
   __shared__ uint32_t s_last, s_win;
   // one merge batch: the weights of both queues' candidates, then its order
   __shared__ uint32_t s_stage[kStage], s_seqw[kStage], s_seqid[kStage];
+  // the two queues of the merge, when the leaves fit: every batch reads
+  // their heads, samples and runs
+  __shared__ uint32_t s_lw[kHLds], s_iw[kHLds];
   __shared__ uint32_t s_blc[32], s_first[32], s_base[32];
   const int t = threadIdx.x, w = t / kWave;
   HScratch H = hscratch_at(scratch + (uint64_t)blockIdx.x * slot_bytes);
@@ -985,9 +989,9 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
             uint32_t *tk = kin; kin = kout; kout = tk;
             uint16_t *ts = sin; sin = sout; sout = ts;
           }
-          for (uint32_t i = t; i < n; i += kHT) { H.l_f[0][i] = kin[i]; H.l_sym[0][i] = sin[i]; }
+          for (uint32_t i = t; i < n; i += kHT) { s_lw[i] = kin[i]; H.l_sym[0][i] = sin[i]; }
           __syncthreads();
-          Lw = H.l_f[0];
+          Lw = s_lw;
           Ls = H.l_sym[0];
         } else {
           const uint32_t *kin = H.a_f;
@@ -1001,7 +1005,13 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
           }
           Lw = kin;
           Ls = sin;
+          if (n <= (uint32_t)kHLds) {
+            for (uint32_t i = t; i < n; i += kHT) s_lw[i] = kin[i];
+            __syncthreads();
+            Lw = s_lw;
+          }
         }
+        uint32_t *const IW = n <= (uint32_t)kHLds ? s_iw : H.iw;
 
         // 3. batched two-queue merge.  Per batch: the weight s of the next
         // merged node from the heads of both queues; the counts cL, cI of
@@ -1015,14 +1025,14 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
           if ((n - lp) + (ni - ip) <= 1) break;
           if (t == 0) {
             const uint32_t x0 = lp < n ? Lw[lp] : ~0u, x1 = lp + 1 < n ? Lw[lp + 1] : ~0u;
-            const uint32_t y0 = ip < ni ? H.iw[ip] : ~0u, y1 = ip + 1 < ni ? H.iw[ip + 1] : ~0u;
+            const uint32_t y0 = ip < ni ? IW[ip] : ~0u, y1 = ip + 1 < ni ? IW[ip + 1] : ~0u;
             s_wsum = min(x0, y0) + (x0 <= y0 ? min(x1, y0) : min(x0, y1));
             s_c1[0] = 0; s_c1[1] = 0; s_c2[0] = 0; s_c2[1] = 0;
           }
           __syncthreads();
           const uint32_t wsum = s_wsum;
           const uint32_t q = (uint32_t)t / (kHT / 2), tq = (uint32_t)t % (kHT / 2);
-          const uint32_t *qa = q ? H.iw + ip : Lw + lp;
+          const uint32_t *qa = q ? IW + ip : Lw + lp;
           const uint32_t qlen = q ? ni - ip : n - lp;
           const uint32_t stp = (qlen + kHT / 2 - 1) / (kHT / 2);
           {
@@ -1046,7 +1056,7 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
           const bool staged = cL + cI <= (uint32_t)kStage;
           if (t == 0) s_aL = 0;
           if (staged) {
-            for (uint32_t e = t; e < cL + cI; e += kHT) s_stage[e] = e < cL ? Lw[lp + e] : H.iw[ip + e - cL];
+            for (uint32_t e = t; e < cL + cI; e += kHT) s_stage[e] = e < cL ? Lw[lp + e] : IW[ip + e - cL];
           }
           __syncthreads();
           uint32_t aL = 0;
@@ -1054,12 +1064,12 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
             uint32_t wv, id, pos;
             if (e < cL) {
               wv = staged ? s_stage[e] : Lw[lp + e];
-              pos = e + (staged ? count_lt(s_stage + cL, cI, wv) : count_lt(H.iw + ip, cI, wv));
+              pos = e + (staged ? count_lt(s_stage + cL, cI, wv) : count_lt(IW + ip, cI, wv));
               id = lp + e;
               aL += pos < 2 * j;
             } else {
               const uint32_t kk = e - cL;
-              wv = staged ? s_stage[e] : H.iw[ip + kk];
+              wv = staged ? s_stage[e] : IW[ip + kk];
               pos = kk + (staged ? count_le(s_stage, cL, wv) : count_le(Lw + lp, cL, wv));
               id = n + ip + kk;
             }
@@ -1076,7 +1086,7 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
             const uint32_t w1 = staged ? s_seqw[2 * i + 1] : H.seqw[2 * i + 1];
             const uint32_t i0 = staged ? s_seqid[2 * i] : H.seqid[2 * i];
             const uint32_t i1 = staged ? s_seqid[2 * i + 1] : H.seqid[2 * i + 1];
-            H.iw[ni + i] = w0 + w1;
+            IW[ni + i] = w0 + w1;
             H.parent[i0] = n + ni + i;
             H.parent[i1] = n + ni + i;
           }
