@@ -868,7 +868,7 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
   __shared__ uint32_t s_tot[kHW];
   __shared__ uint32_t s_red[kHW];
   __shared__ uint32_t s_n, s_maxf, s_maxlen, s_niter, s_lp, s_ip, s_ni, s_aL, s_wsum, s_c1[2], s_c2[2];
-  __shared__ uint32_t s_last, s_win;
+  __shared__ uint32_t s_last, s_win, s_aL2[2];
   // one merge batch: the weights of both queues' candidates, then its order
   __shared__ uint32_t s_stage[kStage], s_seqw[kStage], s_seqid[kStage];
   // the two queues of the merge, when the leaves fit: every batch reads
@@ -1018,9 +1018,67 @@ __global__ __launch_bounds__(kHT) void k_huff(const CField *__restrict__ F, int 
         // leaves and merged nodes of weight <= s (two rounds of samples of
         // each sorted queue, half of the workgroup per queue); the merged
         // order of those nodes by rank search, in LDS when the batch fits.
-        if (t == 0) { s_lp = 0; s_ip = 0; s_ni = 0; s_niter = 0; }
+        if (t == 0) { s_lp = 0; s_ip = 0; s_ni = 0; s_niter = 0; s_aL2[0] = 0; s_aL2[1] = 0; }
         __syncthreads();
-        for (;;) {
+        if (n <= (uint32_t)kHLds) {
+          // Both queues in LDS: every thread finds the batch itself (the
+          // weight of the next merged node from the queues' heads, and the
+          // counts of nodes of weight <= it by binary search), so a batch
+          // takes two barriers: after the merged order, after the new nodes.
+          uint32_t lp = 0, ip = 0, ni = 0, niter = 0;
+          for (;;) {
+            if ((n - lp) + (ni - ip) <= 1) break;
+            const uint32_t x0 = lp < n ? s_lw[lp] : ~0u, x1 = lp + 1 < n ? s_lw[lp + 1] : ~0u;
+            const uint32_t y0 = ip < ni ? s_iw[ip] : ~0u, y1 = ip + 1 < ni ? s_iw[ip + 1] : ~0u;
+            const uint32_t wsum = min(x0, y0) + (x0 <= y0 ? min(x1, y0) : min(x0, y1));
+            const uint32_t cL = count_le(s_lw + lp, n - lp, wsum), cI = count_le(s_iw + ip, ni - ip, wsum);
+            const uint32_t j = (cL + cI) / 2;
+            const bool staged = 2 * j <= (uint32_t)kStage;
+            const uint32_t par = niter & 1u;
+            if (t == 0) s_aL2[par ^ 1u] = 0;  // the next batch's count (last read before this batch)
+            uint32_t aL = 0;
+            for (uint32_t e = t; e < cL + cI; e += kHT) {
+              uint32_t wv, id, pos;
+              if (e < cL) {
+                wv = s_lw[lp + e];
+                pos = e + count_lt(s_iw + ip, cI, wv);
+                id = lp + e;
+                aL += pos < 2 * j;
+              } else {
+                const uint32_t kk = e - cL;
+                wv = s_iw[ip + kk];
+                pos = kk + count_le(s_lw + lp, cL, wv);
+                id = n + ip + kk;
+              }
+              if (pos < 2 * j) {
+                if (staged) { s_seqw[pos] = wv; s_seqid[pos] = id; }
+                else { H.seqw[pos] = wv; H.seqid[pos] = id; }
+              }
+            }
+            aL = wave_sum(aL);
+            if (lane_id() == 0 && aL) atomicAdd(&s_aL2[par], aL);
+            __syncthreads();
+            const uint32_t aLt = s_aL2[par];
+            for (uint32_t i = t; i < j; i += kHT) {
+              const uint32_t w0 = staged ? s_seqw[2 * i] : H.seqw[2 * i];
+              const uint32_t w1 = staged ? s_seqw[2 * i + 1] : H.seqw[2 * i + 1];
+              const uint32_t i0 = staged ? s_seqid[2 * i] : H.seqid[2 * i];
+              const uint32_t i1 = staged ? s_seqid[2 * i + 1] : H.seqid[2 * i + 1];
+              s_iw[ni + i] = w0 + w1;
+              H.parent[i0] = n + ni + i;
+              H.parent[i1] = n + ni + i;
+            }
+            if (t == 0) H.batch_end[niter] = ni + j;
+            __syncthreads();
+            lp += aLt;
+            ip += 2 * j - aLt;
+            ni += j;
+            niter++;
+          }
+          if (t == 0) { s_ni = ni; s_niter = niter; }
+          __syncthreads();
+        }
+        for (; n > (uint32_t)kHLds;) {
           const uint32_t lp = s_lp, ip = s_ip, ni = s_ni;
           if ((n - lp) + (ni - ip) <= 1) break;
           if (t == 0) {
