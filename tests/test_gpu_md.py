@@ -44,6 +44,18 @@ def test_md_lattice_modes(mode, velocities):
     _run(list(snap.values()), 1e-4, mode, "lattice")
 
 
+def test_cpc_rice_parameter_outside_the_mean_window():
+    # Pairs of particles 1e-3 apart, the pairs spread over the box: the
+    # sorted keys alternate tiny and huge deltas, so the cheapest Rice
+    # parameter lies far from the deltas' mean bit length and the device
+    # costs every parameter (the window's lower bounds do not exclude them)
+    rng = np.random.default_rng(3)
+    c = rng.uniform(0, 100, size=(3 * 16384 // 2, 3)).astype(np.float32)
+    p = np.repeat(c, 2, axis=0)
+    p[1::2] += np.float32(1e-3)
+    _run([np.ascontiguousarray(p[:, i]) for i in range(3)], 1e-6, sznb.MD_COMPRESSION, "rice fallback")
+
+
 @pytest.mark.parametrize("mode", [sznb.MD_TRADEOFF, sznb.MD_COMPRESSION])
 @pytest.mark.parametrize("eb", [1e-2, 1e-5])
 def test_md_error_bounds(mode, eb):
