@@ -250,8 +250,6 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
   // 28-31: the counting pass steps over all of them at once)
   __shared__ uint8_t s_len[1u << kLutBits];  // length of a code within the window, 0 if none
   __shared__ uint16_t s_sym[1u << kLutBits];  // its symbol
-  __shared__ uint32_t s_nmulti;
-  if (t == 0) s_nmulti = 0;
   uint32_t *lut = df.lut + (uint64_t)k * (2u << kLutBits);
   uint32_t *lut2 = lut + (1u << kLutBits);
   uint32_t ents[(1u << kLutBits) / kThreads];
@@ -279,11 +277,21 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
     s_sym[e] = (uint16_t)(ent & 0xffffu);
   }
   __syncthreads();
-  // second table: up to three leading codes of the window whose symbols are
-  // within 127 of 32768, as signed bytes, their count and total length
+  // second table, in one of two forms: up to three leading codes of the
+  // window whose symbols are within 127 of 32768, as signed bytes (bits
+  // 0-23), their count (24-25) and total length (26-29); or up to six whose
+  // symbols are within 7 of 32768, as signed nibbles (0-23), count (24-26)
+  // and length (27-30).  The form that yields more symbols over the 4096
+  // windows is kept.
+  __shared__ uint32_t s_sum[2], s_nm[2];
+  __shared__ uint32_t s_e6[1u << kLutBits];
+  if (t < 2) { s_sum[t] = 0; s_nm[t] = 0; }
+  __syncthreads();
+  uint32_t sum3 = 0, sum6 = 0, nm3 = 0, nm6 = 0;
+#pragma unroll
   for (uint32_t e = t, j = 0; e < (1u << kLutBits); e += kThreads, j++) {
-    uint32_t pos = 0, cnt = 0, n2 = 0, l2 = 0, d3 = 0;
-    bool small = true;
+    uint32_t pos = 0, cnt = 0, n2 = 0, l2 = 0, d3 = 0, n6 = 0, l6 = 0, d6 = 0;
+    bool small = true, tiny = true;
     for (;;) {
       // code at bit pos of the window (bits past the window read as zero;
       // a code is counted only if it ends inside the window)
@@ -298,17 +306,41 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
       } else {
         small = false;
       }
+      if (tiny && n6 < 6u && dv >= -8 && dv <= 7) {
+        d6 |= ((uint32_t)dv & 15u) << (4 * n6);
+        n6++;
+        l6 = pos + l;
+      } else {
+        tiny = false;
+      }
       pos += l;
       cnt++;
     }
     lut[e] = ents[j] | (cnt << 24) | (pos << 28);
     lut2[e] = d3 | (n2 << 24) | (l2 << 26);
-    if (n2 >= 2u) atomicAdd(&s_nmulti, 1u);
+    s_e6[e] = d6 | (n6 << 24) | (l6 << 27);
+    sum3 += n2;
+    sum6 += n6;
+    nm3 += n2 >= 2u;
+    nm6 += n6 >= 2u;
+  }
+  sum3 = wave_sum(sum3);
+  sum6 = wave_sum(sum6);
+  nm3 = wave_sum(nm3);
+  nm6 = wave_sum(nm6);
+  if (lane_id() == 0) {
+    atomicAdd(&s_sum[0], sum3);
+    atomicAdd(&s_sum[1], sum6);
+    atomicAdd(&s_nm[0], nm3);
+    atomicAdd(&s_nm[1], nm6);
   }
   __syncthreads();
+  const uint32_t form = s_sum[1] > s_sum[0] ? 1u : 0u;
+  if (form)
+    for (uint32_t e = t; e < (1u << kLutBits); e += kThreads) lut2[e] = s_e6[e];
   // the multi-symbol step pays for its extra lookup when at least a quarter
   // of the windows (of the code's own probability mass) offer one
-  if (t == 0 && s_nmulti >= (1u << kLutBits) / 4) atomicOr(&st->multi, 1u << k);
+  if (t == 0 && s_nm[form] >= (1u << kLutBits) / 4) atomicOr(&st->multi, (1u << k) | (form << (4 + k)));
   uint32_t *slow = df.slow + (uint64_t)k * kSlowWords;
   if (t < 32) {
     slow[t] = s_first[t];
@@ -377,6 +409,7 @@ struct DecTab {
   const uint32_t *lut;     // LDS: 4096 first-level entries
   const uint32_t *lut2;    // LDS: 4096 small-symbol entries
   bool multi;              // use them
+  bool multi6;             // in the six-nibble form
   const uint32_t *first;   // LDS: first canonical code of each length
   const uint32_t *base;    // LDS: canonical index of that code
   const uint64_t *limit;   // LDS: end of the left-justified code range of each length
@@ -585,7 +618,30 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
     if (p < e && i < len) {
       BitReader br;
       br_init(br, wp, cw, p);
-      if (T.multi) {
+      if (T.multi && T.multi6) {
+        while (p < e && i < len) {
+          const uint32_t win = br_peek(br);
+          const uint32_t m = T.lut2[win >> (32 - kLutBits)];
+          const uint32_t n6 = (m >> 24) & 7u, l6 = (m >> 27) & 15u;
+          uint32_t ln, adv;
+          if (n6 >= 2u && p + l6 <= e && i + n6 <= len) {  // two to six tiny symbols at once
+#pragma unroll
+            for (uint32_t u = 0; u < 6u; u++)
+              if (u < n6) q16[qaddr(i + u)] = (uint16_t)(kRadius + ((int32_t)(m << (28 - 4 * u)) >> 28));
+            ln = l6;
+            adv = n6;
+          } else {
+            const uint32_t r = decode_sym(T, win);
+            ln = (r >> 16) & 31u;
+            if (r & kLutInvalid) invalid = 1;
+            q16[qaddr(i)] = (uint16_t)(r & 0xffffu);
+            adv = 1;
+          }
+          p += ln;
+          br_skip(br, ln);
+          i += adv;
+        }
+      } else if (T.multi) {
         while (p < e && i < len) {
           const uint32_t win = br_peek(br);
           const uint32_t m = T.lut2[win >> (32 - kLutBits)];
@@ -748,6 +804,7 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     T2.lut = s_lut;
     T2.lut2 = s_lut + (1u << kLutBits);
     T2.multi = lut_words > (1u << kLutBits) && ((st->multi >> k) & 1u);
+    T2.multi6 = (st->multi >> (4 + k)) & 1u;
     T2.first = s_first;
     T2.base = s_base;
     T2.limit = s_limit;
