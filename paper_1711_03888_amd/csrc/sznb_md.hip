@@ -228,15 +228,22 @@ __global__ __launch_bounds__(kMT) void md_sort(uint64_t *kin, uint32_t *iin, uin
         if (i < end) v[c] = s_v[i];
       }
     }
-    // element v & 16383 of the input takes position i
+    // element v & 16383 of the input takes position i; every gather load
+    // is issued before the first store (a store could alias a later load,
+    // which would otherwise wait for it)
+    uint64_t kv[kPL];
+    uint32_t iv[kPL];
 #pragma unroll
     for (int c = 0; c < kPL; c++) {
       const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
-      if (i < end) {
-        const uint32_t src = (uint32_t)(v[c] & 16383u);
-        kb[i] = ka[src];
-        ib[i] = ia[src];
-      }
+      const uint32_t src = i < end ? (uint32_t)(v[c] & 16383u) : 0u;
+      kv[c] = ka[src];
+      iv[c] = ia[src];
+    }
+#pragma unroll
+    for (int c = 0; c < kPL; c++) {
+      const uint32_t i = beg + (uint32_t)c * kWave + lane_id();
+      if (i < end) { kb[i] = kv[c]; ib[i] = iv[c]; }
     }
     return;
   }
