@@ -101,7 +101,7 @@ int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uin
 
 /* For callers that cannot allocate device memory (code between allocations
  * of a serving loop, harnesses that forbid hipMalloc): sznb_decompress
- * without a workspace argument.  The library keeps a fixed 4 MiB workspace
+ * without a workspace argument.  The library keeps a fixed 8 MiB workspace
  * per GPU in device memory for the life of the process and never allocates
  * in this call; fields of more than SZNB_NOALLOC_MAX_N values are refused
  * with SZNB_ENOSPC.  Every call on one GPU shares that GPU's workspace:

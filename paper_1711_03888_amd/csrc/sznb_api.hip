@@ -30,9 +30,10 @@ uint64_t hscratch_bytes_host();
 __global__ void d_prep(const DField *, uint32_t);
 __global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
-__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *, uint32_t *);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int, const uint32_t *);
-__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t);
+__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
+                         uint32_t);
 
 template <int E>
 __global__ void k_features(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, float *, uint64_t *,
@@ -119,7 +120,7 @@ __device__ uint32_t g_logt[16385];
 // in device memory, one copy per GPU for the life of the process.  Host code
 // reaches it only through the address hipGetSymbolAddress gives per device
 // (DevInfo::scratch), never through its name.
-constexpr uint64_t kScratchBytes = 4ull << 20;
+constexpr uint64_t kScratchBytes = 8ull << 20;
 static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 struct DevInfo {
@@ -803,7 +804,7 @@ static int set_selector_impl(const float *h_params, float tau) {
 
 struct DLayout {
   uint64_t gctl, states, fields, tbase, heads, total;
-  std::vector<uint64_t> boff, order, lut, slow, syms, nbmax;
+  std::vector<uint64_t> desc, lut, slow, syms, nbmax;
 };
 
 static DLayout decompress_layout(int nf, const uint64_t *n) {
@@ -812,13 +813,12 @@ static DLayout decompress_layout(int nf, const uint64_t *n) {
   L.gctl = o; o = al256(o + sizeof(GCtl));
   L.states = o; o = al256(o + kStateStride * nf);
   L.fields = o; o = al256(o + sizeof(DField) * nf);
-  L.tbase = o; o = al256(o + 4ull * (3 * nf + 1));
+  L.tbase = o; o = al256(o + 4ull * (6 * nf + 3));
   L.heads = o; o = al256(o + 16ull * nf);
-  L.boff.resize(nf); L.order.resize(nf); L.lut.resize(nf); L.slow.resize(nf); L.syms.resize(nf); L.nbmax.resize(nf);
+  L.desc.resize(nf); L.lut.resize(nf); L.slow.resize(nf); L.syms.resize(nf); L.nbmax.resize(nf);
   for (int f = 0; f < nf; f++) {
     L.nbmax[f] = (n[f] + 1023) / 1024;
-    L.boff[f] = o; o = al256(o + 4ull * L.nbmax[f]);
-    L.order[f] = o; o = al256(o + 4ull * L.nbmax[f]);
+    L.desc[f] = o; o = al256(o + 16ull * L.nbmax[f]);
     L.lut[f] = o; o = al256(o + 4ull * 3 * (2u << kLutBits));  // per predictor: first-code table, small-symbol table
     L.slow[f] = o; o = al256(o + 4ull * 3 * kSlowWords);
     L.syms[f] = o; o = al256(o + 2ull * 3 * kNSyms);
@@ -871,8 +871,7 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
     d.n = n[f];
     d.nblocks_max = (uint32_t)L.nbmax[f];
     d.st = reinterpret_cast<DState *>(ws + L.states + kStateStride * f);
-    d.boff = reinterpret_cast<uint32_t *>(ws + L.boff[f]);
-    d.order = reinterpret_cast<uint32_t *>(ws + L.order[f]);
+    d.desc = reinterpret_cast<u32x4 *>(ws + L.desc[f]);
     d.lut = reinterpret_cast<uint32_t *>(ws + L.lut[f]);
     d.slow = reinterpret_cast<uint32_t *>(ws + L.slow[f]);
     d.syms = reinterpret_cast<uint16_t *>(ws + L.syms[f]);
@@ -942,6 +941,8 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
   return SZNB_OK;
 }
 
+constexpr uint32_t kTaskBlocks = 8, kTailBlocks = 2;
+
 // Kernels only (capturable): streams whose block size exceeds the planned
 // one are reported corrupt rather than decoded.
 static int decompress_run(const DLaunch &P, hipStream_t stream) {
@@ -951,9 +952,14 @@ static int decompress_run(const DLaunch &P, hipStream_t stream) {
   SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(1024), 0, stream, D, P.smax);
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
   uint32_t *nconst = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->pad[0];
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, P.dw, tbase, ticket, nconst);
+  // decode tasks of kTaskBlocks blocks per wave of the workgroup, and of one
+  // block per wave over the last kTailBlocks blocks per resident wave
+  const uint32_t tbig = P.dw * kTaskBlocks, tsmall = P.dw, rtail = (uint32_t)P.grid * P.dw * kTailBlocks;
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, tbig, tsmall, rtail, tbase, ticket,
+              nconst);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf, nconst);
-  SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.dw, P.smax,
+  SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, tbig, tsmall,
+              P.smax,
               P.symcap, ticket, P.lut_words);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }

@@ -1,7 +1,8 @@
 // Decompression kernels of the sznb library (gfx950, wave64).
 //
-//   d_prep     header validation, block word offsets, blocks grouped by
-//              predictor (one workgroup per stream)
+//   d_prep     header validation, one descriptor per block (id, payload
+//              word offset, codeword and escape counts, first value) in
+//              predictor-grouped order (one workgroup per stream)
 //   d_tables   canonical decode tables per (stream, predictor): a 4096-entry
 //              first-level table and per-length limits for longer codes
 //   d_tasks    task prefix over (stream, predictor) groups
@@ -183,19 +184,23 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
   }
   uint32_t gstart[3] = {0, tot[1], tot[1] + tot[2]};
   uint32_t run = ex[0], gpos[3] = {gstart[0] + ex[1], gstart[1] + ex[2], gstart[2] + ex[3]};
-  const gptr<uint32_t> boff = G(df.boff), order = G(df.order);
+  // each block's descriptor goes to its predictor group's next slot, so a
+  // decoding wave reads everything it needs to start a block in one load
+  const gptr<u32x4> desc = G(df.desc);
+  const uint64_t opf = st->off_pfirst;
   for (uint32_t b0 = lo; b0 < hi; b0 += kPrepBatch) {
-    uint32_t cwv[kPrepBatch], nev[kPrepBatch], kv[kPrepBatch];
+    uint32_t cwv[kPrepBatch], nev[kPrepBatch], kv[kPrepBatch], p0v[kPrepBatch];
     batch(b0, cwv, nev, kv);
+#pragma unroll
+    for (uint32_t j = 0; j < kPrepBatch; j++) p0v[j] = rd32(gin, opf + 4ull * min(b0 + j, hi - 1));
 #pragma unroll
     for (uint32_t j = 0; j < kPrepBatch; j++) {
       const uint32_t b = b0 + j;
       if (b >= hi) break;
-      boff[b] = run;
       const uint32_t k = kv[j];
-      run += skip_words(cwv[j], k == 0 ? mlen[0] : k == 1 ? mlen[1] : mlen[2]) + cwv[j] + nev[j];
       const uint32_t gp = k == 0 ? gpos[0]++ : k == 1 ? gpos[1]++ : gpos[2]++;
-      order[gp] = b;
+      desc[gp] = u32x4{b, run, cwv[j] | (nev[j] << 16), p0v[j]};
+      run += skip_words(cwv[j], k == 0 ? mlen[0] : k == 1 ? mlen[1] : mlen[2]) + cwv[j] + nev[j];
     }
   }
   if (t == 0) {
@@ -352,41 +357,76 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
 
 // ---------------------------------------------------------------- tasks
 
-// tbase[p] for p = 3 f + k: first decode task of (stream f, predictor k); a
-// task is up to `dw` consecutive blocks of one group.
-__global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t dw,
-                                                    uint32_t *tbase, uint32_t *ticket, uint32_t *nconst) {
+// Decode tasks.  The groups' blocks, taken in (stream, predictor) order,
+// form one sequence of C blocks; a task is a run of blocks of one group, of
+// up to `tbig` blocks before position cut = C - rtail and of up to `tsmall`
+// after it, so that the last tasks of the launch are short.  Written:
+//   tbase[p], p = 3 f + k <= np   first task of group p (tbase[np]: total)
+//   tbase[np + 1 + p], p <= np    first block of group p in the sequence
+//   tbase[2 np + 2]               cut
+__device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tot, uint32_t &total) {
+  const int w = threadIdx.x / kWave;
+  const uint32_t inc = wave_incl_scan(v);
+  __syncthreads();  // the previous scan's totals have been read
+  if (lane_id() == kWave - 1) s_tot[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - v;
+  total = 0;
+  for (int i = 0; i < kThreads / kWave; i++) {
+    if (i < w) run += s_tot[i];
+    total += s_tot[i];
+  }
+  return run;
+}
+
+__global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t tbig,
+                                                    uint32_t tsmall, uint32_t rtail, uint32_t *tbase,
+                                                    uint32_t *ticket, uint32_t *nconst) {
   __shared__ uint32_t s_tot[kThreads / kWave];
   __shared__ uint32_t s_const;
-  const int t = threadIdx.x, w = t / kWave;
+  const int t = threadIdx.x;
   const int np = 3 * nf;
   const int per = (np + kThreads - 1) / kThreads;
   if (t == 0) s_const = 0;
   __syncthreads();
+  auto blocks = [&](int p) -> uint32_t {
+    const DState *st = D[p / 3].st;
+    return st->status == 0 && !st->is_const ? st->grp_count[p % 3] : 0u;
+  };
   uint32_t loc = 0, ncon = 0;
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
+      loc += blocks(p);
       const DState *st = D[p / 3].st;
-      if (st->status == 0 && !st->is_const) loc += (st->grp_count[p % 3] + dw - 1) / dw;
       if (p % 3 == 0 && st->status == 0 && st->is_const) ncon++;
     }
   }
   if (ncon) atomicAdd(&s_const, ncon);
-  const uint32_t inc = wave_incl_scan(loc);
-  if (lane_id() == kWave - 1) s_tot[w] = inc;
-  __syncthreads();
-  uint32_t run = inc - loc;
-  for (int i = 0; i < w; i++) run += s_tot[i];
+  uint32_t C;
+  uint32_t pos = wg_excl_scan(loc, s_tot, C);
+  const uint32_t cut = C > rtail ? C - rtail : 0u;
+  uint32_t ntask = 0;
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
-      tbase[p] = run;
-      const DState *st = D[p / 3].st;
-      if (st->status == 0 && !st->is_const) run += (st->grp_count[p % 3] + dw - 1) / dw;
+      const uint32_t c = blocks(p), a = min(c, cut > pos ? cut - pos : 0u);
+      tbase[np + 1 + p] = pos;
+      ntask += (a + tbig - 1) / tbig + (c - a + tsmall - 1) / tsmall;
+      pos += c;
     }
   }
-  if (t == kThreads - 1) { tbase[np] = run; *ticket = 0; }
+  uint32_t T;
+  uint32_t run = wg_excl_scan(ntask, s_tot, T);
+  for (int j = 0; j < per; j++) {
+    const int p = t * per + j;
+    if (p < np) {
+      const uint32_t c = blocks(p), b0 = tbase[np + 1 + p], a = min(c, cut > b0 ? cut - b0 : 0u);
+      tbase[p] = run;
+      run += (a + tbig - 1) / tbig + (c - a + tsmall - 1) / tsmall;
+    }
+  }
+  if (t == 0) { tbase[np] = T; tbase[2 * np + 1] = C; tbase[2 * np + 2] = cut; *ticket = 0; }
   __syncthreads();
   if (t == 0) *nconst = s_const;
 }
@@ -495,18 +535,16 @@ __device__ inline uint32_t decode_sym(const DecTab &T, uint32_t win) {
 // the reconstructed floats are stored straight from registers, coalesced.
 __device__ __forceinline__ uint32_t qaddr(uint32_t e) { return e ^ (((e >> 6) & 31u) << 1); }
 
-__device__ __forceinline__ void decode_block(const DField &df, gptr<const DState> st, const DecTab &T, uint32_t b,
-                                             uint16_t *q16, int *bad_flag) {
+__device__ __forceinline__ void decode_block(const DField &df, gptr<const DState> st, const DecTab &T, u32x4 dsc,
+                                             uint32_t k, uint16_t *q16, int *bad_flag) {
   const uint32_t l = lane_id();
   const gptr<const uint8_t> in = G(df.in);
-  const uint32_t S = st->S;
+  const uint32_t S = st->S, b = dsc.x;
   const uint32_t len = (uint32_t)min((uint64_t)S, st->n - (uint64_t)b * S);
-  const uint32_t cw = rd16(in, st->off_cwords + 2ull * b);
-  const uint32_t ne = rd16(in, st->off_nesc + 2ull * b);
-  const uint32_t k = st->policy >= 2 ? in[st->off_pred + b] : st->policy;
-  const int32_t p0 = (int32_t)rd32(in, st->off_pfirst + 4ull * b);
+  const uint32_t cw = dsc.z & 0xffffu, ne = dsc.z >> 16;
+  const int32_t p0 = (int32_t)dsc.w;
   const uint32_t R = n_ranges(cw), swd = skip_width(T.maxlen), skw = skip_words(cw, T.maxlen);
-  const gptr<const uint32_t> sk = reinterpret_cast<gptr<const uint32_t>>(in + st->off_payload) + G(df.boff)[b];
+  const gptr<const uint32_t> sk = reinterpret_cast<gptr<const uint32_t>>(in + st->off_payload) + dsc.y;
   const gptr<const uint32_t> wp = sk + skw;
   const gptr<const uint32_t> esc = wp + cw;
   uint32_t invalid = 0;
@@ -733,12 +771,13 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   __builtin_amdgcn_wave_barrier();
 }
 
-// dw waves per workgroup.  Dynamic LDS: lut (4096 words), lut2 (4096 words
+// A workgroup of dw waves takes the tasks d_tasks laid out from a global
+// ticket.  Dynamic LDS: lut (4096 words), lut2 (4096 words
 // when some codebook is small enough to use it) | first, base (32
 // words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
 // code regions of 2 smax bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
-                         uint32_t dw, uint32_t smax, uint32_t symcap, uint32_t *ticket, uint32_t lut_words) {
+                         uint32_t tbig, uint32_t tsmall, uint32_t smax, uint32_t symcap, uint32_t *ticket, uint32_t lut_words) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
   uint32_t *s_first = s_lut + lut_words;
@@ -746,18 +785,16 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
   uint64_t *s_limit = reinterpret_cast<uint64_t *>(s_base + 32);
   uint16_t *s_syms = reinterpret_cast<uint16_t *>(s_limit + 32);
   uint8_t *regs = reinterpret_cast<uint8_t *>(s_syms) + ((2u * symcap + 15u) & ~15u);
-  __shared__ uint32_t s_task;
+  __shared__ uint32_t s_task, s_next;
   const int t = threadIdx.x;
-  const uint32_t w = t / kWave;
   const int np = 3 * nf;
   const uint32_t T = tbase[np];
   int cur = -1;
   bool syms_lds = false;
   for (;;) {
-    if (t == 0) s_task = atomicAdd(ticket, 1u);
+    if (t == 0) { s_task = atomicAdd(ticket, 1u); s_next = 0; }
     __syncthreads();
     const uint32_t task = s_task;
-    __syncthreads();
     if (task >= T) break;
     // pair of this task
     int lo = 0, hi = np - 1;
@@ -812,13 +849,25 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     T2.gsyms = G(df.syms) + (uint64_t)k * kNSyms;
     T2.syms_lds = syms_lds;
     T2.maxlen = st->maxlen[k];
-    const uint32_t idx = (task - tbase[pair]) * dw + w;
-    if (idx < st->grp_count[k]) {
-      const uint32_t b = G(df.order)[st->grp_start[k] + idx];
+    // the task's run of the group's blocks
+    const uint32_t b0 = tbase[np + 1 + pair], c = tbase[np + 2 + pair] - b0, cut = tbase[2 * np + 2];
+    const uint32_t a = min(c, cut > b0 ? cut - b0 : 0u), nbig = (a + tbig - 1) / tbig, i = task - tbase[pair];
+    const uint32_t first = i < nbig ? i * tbig : a + (i - nbig) * tsmall;
+    const uint32_t cnt = i < nbig ? min(tbig, a - first) : min(tsmall, c - first);
+    // its blocks go to the waves one at a time as they come free, so a wave
+    // that drew short blocks takes more of them
+    uint16_t *q16 = reinterpret_cast<uint16_t *>(regs + (uint64_t)(t / kWave) * 2u * smax);
+    for (;;) {
+      uint32_t j = 0;
+      if (lane_id() == 0) j = atomicAdd(&s_next, 1u);
+      j = __builtin_amdgcn_readfirstlane(j);
+      if (j >= cnt) break;
+      const u32x4 dsc = G(static_cast<const u32x4 *>(df.desc))[st->grp_start[k] + first + j];
       int bad = 0;
-      decode_block(df, st, T2, b, reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * smax), &bad);
+      decode_block(df, st, T2, dsc, (uint32_t)k, q16, &bad);
       if (bad && lane_id() == 0) atomicCAS(&df.st->status, 0, SZNB_ECORRUPT);
     }
+    __syncthreads();  // every wave is past the task before its counter is reset
   }
 }
 

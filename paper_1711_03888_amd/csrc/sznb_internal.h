@@ -57,6 +57,7 @@ __device__ __forceinline__ gptr<T> G(T *p) {
   return (gptr<T>)p;
 }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Read-only view through the scalar data cache (constant address space),
 // for per-field parameters that nothing writes while the reading kernel
 // runs.  Uniform loads through it are scalar loads, counted apart from
@@ -171,7 +172,7 @@ struct alignas(64) DState {
   uint32_t nsym[3], maxlen[3];
   uint64_t book_off[3];
   uint32_t grp_count[3];  // blocks per predictor
-  uint32_t grp_start[3];  // first entry of each predictor's run in `order`
+  uint32_t grp_start[3];  // first entry of each predictor's run in `desc`
 };
 
 struct alignas(16) DField {
@@ -182,8 +183,8 @@ struct alignas(16) DField {
   uint32_t nblocks_max;
   uint32_t skip;          // set on the device: this descriptor decodes nothing
   DState *st;
-  uint32_t *boff;         // payload word offset of every block
-  uint32_t *order;        // block ids grouped by predictor
+  u32x4 *desc;            // per block, grouped by predictor: {block id, payload
+                          // word offset, codewords | escapes << 16, first value}
   uint32_t *lut;          // 3 x (4096 first-code entries + 4096 small-symbol entries)
   uint32_t *slow;         // 3 x (32 first + 32 base + 64 limit words)
   uint16_t *syms;         // 3 x 65536 canonical symbols
