@@ -30,10 +30,9 @@ uint64_t hscratch_bytes_host();
 __global__ void d_prep(const DField *, uint32_t);
 __global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
-__global__ void d_tasks(const DField *, int, uint32_t, uint32_t, uint32_t, uint32_t *, uint32_t *, uint32_t *);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int, const uint32_t *);
-__global__ void d_decode(const DField *, int, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t *,
-                         uint32_t);
+__global__ void d_decode(const DField *, int, uint32_t *, uint32_t, uint32_t, uint32_t);
 
 template <int E>
 __global__ void k_features(const CField *, int, const uint64_t *, uint64_t, const uint32_t *, float *, uint64_t *,
@@ -813,7 +812,8 @@ static DLayout decompress_layout(int nf, const uint64_t *n) {
   L.gctl = o; o = al256(o + sizeof(GCtl));
   L.states = o; o = al256(o + kStateStride * nf);
   L.fields = o; o = al256(o + sizeof(DField) * nf);
-  L.tbase = o; o = al256(o + 4ull * (6 * nf + 3));
+  // group offsets, piece tables and counters
+  L.tbase = o; o = al256(o + 4ull * (6ull * nf + 3 + 3ull * (3ull * nf + kMaxDecodeGrid)));
   L.heads = o; o = al256(o + 16ull * nf);
   L.desc.resize(nf); L.lut.resize(nf); L.slow.resize(nf); L.syms.resize(nf); L.nbmax.resize(nf);
   for (int f = 0; f < nf; f++) {
@@ -937,30 +937,22 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
   P.symcap = symcap;
   P.dw = dw;
   P.lds = lds;
-  P.grid = dv->cus * (int)std::max<size_t>(1, lds_cu / lds);
+  P.grid = (int)std::min<size_t>(kMaxDecodeGrid, (size_t)dv->cus * std::max<size_t>(1, lds_cu / lds));
   return SZNB_OK;
 }
-
-constexpr uint32_t kTaskBlocks = 8, kTailBlocks = 2;
 
 // Kernels only (capturable): streams whose block size exceeds the planned
 // one are reported corrupt rather than decoded.
 static int decompress_run(const DLaunch &P, hipStream_t stream) {
   const DField *D = reinterpret_cast<const DField *>(P.ws + P.L.fields);
   uint32_t *tbase = reinterpret_cast<uint32_t *>(P.ws + P.L.tbase);
-  uint32_t *ticket = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->ticket;
   SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(1024), 0, stream, D, P.smax);
   SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
   uint32_t *nconst = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->pad[0];
-  // decode tasks of kTaskBlocks blocks per wave of the workgroup, and of one
-  // block per wave over the last kTailBlocks blocks per resident wave
-  const uint32_t tbig = P.dw * kTaskBlocks, tsmall = P.dw, rtail = (uint32_t)P.grid * P.dw * kTailBlocks;
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, tbig, tsmall, rtail, tbase, ticket,
-              nconst);
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, (uint32_t)P.grid, tbase, nconst);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf, nconst);
-  SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, tbig, tsmall,
-              P.smax,
-              P.symcap, ticket, P.lut_words);
+  SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.smax,
+              P.symcap, P.lut_words);
   return hipGetLastError() == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
 

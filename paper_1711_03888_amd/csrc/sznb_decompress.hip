@@ -5,7 +5,8 @@
 //              predictor-grouped order (one workgroup per stream)
 //   d_tables   canonical decode tables per (stream, predictor): a 4096-entry
 //              first-level table and per-length limits for longer codes
-//   d_tasks    task prefix over (stream, predictor) groups
+//   d_tasks    group offsets and the pieces (runs of one group's blocks,
+//              one per decode workgroup) with their counters
 //   d_decode   one wave per block: parallel Huffman decode of the block's
 //              ranges from the skip-table entry points (one lane per range),
 //              escapes, inverse prediction by a wave scan of affine prefix
@@ -357,13 +358,16 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
 
 // ---------------------------------------------------------------- tasks
 
-// Decode tasks.  The groups' blocks, taken in (stream, predictor) order,
-// form one sequence of C blocks; a task is a run of blocks of one group, of
-// up to `tbig` blocks before position cut = C - rtail and of up to `tsmall`
-// after it, so that the last tasks of the launch are short.  Written:
-//   tbase[p], p = 3 f + k <= np   first task of group p (tbase[np]: total)
-//   tbase[np + 1 + p], p <= np    first block of group p in the sequence
-//   tbase[2 np + 2]               cut
+// Decode pieces.  The groups' blocks, taken in (stream, predictor) order,
+// form one sequence of C blocks; each group is cut into pieces of at most
+// L = ceil(C / G) blocks for a decode grid of G workgroups, so there are at
+// most G + np pieces.  Written into tb (np = 3 nf groups):
+//   tb[p], p <= np             first block of group p in the sequence (C)
+//   tb[np + 1 + p], p <= np    first piece of group p (total Q)
+//   tb[2 np + 2]               L
+//   tb[2 np + 3 + q]           group of piece q          (q < Q <= np + G)
+//   tb[2 np + 3 + QM + q]      blocks of piece q         (QM = np + kMaxDecodeGrid)
+//   tb[2 np + 3 + 2 QM + q]    blocks of piece q handed out, zeroed here
 __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tot, uint32_t &total) {
   const int w = threadIdx.x / kWave;
   const uint32_t inc = wave_incl_scan(v);
@@ -379,13 +383,14 @@ __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tot, uint32_t &t
   return run;
 }
 
-__global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t tbig,
-                                                    uint32_t tsmall, uint32_t rtail, uint32_t *tbase,
-                                                    uint32_t *ticket, uint32_t *nconst) {
+__global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t grid,
+                                                    uint32_t *tb, uint32_t *nconst) {
   __shared__ uint32_t s_tot[kThreads / kWave];
   __shared__ uint32_t s_const;
   const int t = threadIdx.x;
   const int np = 3 * nf;
+  const uint32_t QM = (uint32_t)np + kMaxDecodeGrid;
+  uint32_t *pgrp = tb + 2 * np + 3, *plen = pgrp + QM, *ctr = plen + QM;
   const int per = (np + kThreads - 1) / kThreads;
   if (t == 0) s_const = 0;
   __syncthreads();
@@ -405,28 +410,32 @@ __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D
   if (ncon) atomicAdd(&s_const, ncon);
   uint32_t C;
   uint32_t pos = wg_excl_scan(loc, s_tot, C);
-  const uint32_t cut = C > rtail ? C - rtail : 0u;
-  uint32_t ntask = 0;
+  const uint32_t L = max(1u, (uint32_t)(((uint64_t)C + grid - 1) / grid));
+  uint32_t npc = 0;
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
-      const uint32_t c = blocks(p), a = min(c, cut > pos ? cut - pos : 0u);
-      tbase[np + 1 + p] = pos;
-      ntask += (a + tbig - 1) / tbig + (c - a + tsmall - 1) / tsmall;
+      tb[p] = pos;
+      const uint32_t c = blocks(p);
       pos += c;
+      npc += (c + L - 1) / L;
     }
   }
-  uint32_t T;
-  uint32_t run = wg_excl_scan(ntask, s_tot, T);
+  uint32_t Q;
+  uint32_t q = wg_excl_scan(npc, s_tot, Q);
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
-      const uint32_t c = blocks(p), b0 = tbase[np + 1 + p], a = min(c, cut > b0 ? cut - b0 : 0u);
-      tbase[p] = run;
-      run += (a + tbig - 1) / tbig + (c - a + tsmall - 1) / tsmall;
+      tb[np + 1 + p] = q;
+      const uint32_t c = blocks(p);
+      for (uint32_t i = 0; i * L < c; i++, q++) {
+        pgrp[q] = (uint32_t)p;
+        plen[q] = min(L, c - i * L);
+        ctr[q] = 0;
+      }
     }
   }
-  if (t == 0) { tbase[np] = T; tbase[2 * np + 1] = C; tbase[2 * np + 2] = cut; *ticket = 0; }
+  if (t == 0) { tb[np] = C; tb[2 * np + 1] = Q; tb[2 * np + 2] = L; }
   __syncthreads();
   if (t == 0) *nconst = s_const;
 }
@@ -771,13 +780,23 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   __builtin_amdgcn_wave_barrier();
 }
 
-// A workgroup of dw waves takes the tasks d_tasks laid out from a global
-// ticket.  Dynamic LDS: lut (4096 words), lut2 (4096 words
-// when some codebook is small enough to use it) | first, base (32
-// words each) | limit (32 u64) | symbols (symcap u16, when they fit) | dw
-// code regions of 2 smax bytes.
-__global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *__restrict__ tbase,
-                         uint32_t tbig, uint32_t tsmall, uint32_t smax, uint32_t symcap, uint32_t *ticket, uint32_t lut_words) {
+// Workgroup g of G starts on piece g: its waves take three quarters of the
+// piece's blocks in turn and the rest one at a time from the piece's
+// counter, so a wave that drew short blocks takes more, and the workgroup
+// meets at a barrier only when the piece is used up.  It then helps with the
+// piece with the most counter-served blocks left, until none has any.  Dynamic LDS: lut (4096 words), lut2 (4096 words when some
+// codebook is small enough to use it) | first, base (32 words each) | limit
+// (32 u64) | symbols (symcap u16, when they fit) | dw code regions of 2 smax
+// bytes.
+// Blocks of piece q (of c blocks) that its own workgroup decodes without the
+// counter: three quarters, in whole turns of the nw waves.  Pieces past the
+// grid have no workgroup of their own and are all counter-served.
+__device__ inline uint32_t static_blocks(uint32_t q, uint32_t c, uint32_t nw) {
+  return q < gridDim.x ? c * 3u / 4u / nw * nw : 0u;
+}
+
+__global__ void d_decode(const DField *__restrict__ D, int nf, uint32_t *tb, uint32_t smax, uint32_t symcap,
+                         uint32_t lut_words) {
   extern __shared__ __align__(16) uint8_t smem[];
   uint32_t *s_lut = reinterpret_cast<uint32_t *>(smem);
   uint32_t *s_first = s_lut + lut_words;
@@ -785,28 +804,50 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
   uint64_t *s_limit = reinterpret_cast<uint64_t *>(s_base + 32);
   uint16_t *s_syms = reinterpret_cast<uint16_t *>(s_limit + 32);
   uint8_t *regs = reinterpret_cast<uint8_t *>(s_syms) + ((2u * symcap + 15u) & ~15u);
-  __shared__ uint32_t s_task, s_next;
+  __shared__ uint64_t s_red[1024 / kWave];
   const int t = threadIdx.x;
+  const uint32_t w = t / kWave, nw = blockDim.x / kWave;
   const int np = 3 * nf;
-  const uint32_t T = tbase[np];
+  const uint32_t QM = (uint32_t)np + kMaxDecodeGrid;
+  const uint32_t *pgrp = tb + 2 * np + 3, *plen = pgrp + QM;
+  uint32_t *ctr = tb + 2 * np + 3 + 2 * QM;
+  const uint32_t C = tb[np], Q = tb[2 * np + 1], L = tb[2 * np + 2];
+  if (Q == 0) return;
+  const uint32_t r0 = blockIdx.x % Q;
+  uint32_t piece = blockIdx.x < Q ? blockIdx.x : Q;  // Q: choose below
   int cur = -1;
   bool syms_lds = false;
-  for (;;) {
-    if (t == 0) { s_task = atomicAdd(ticket, 1u); s_next = 0; }
-    __syncthreads();
-    const uint32_t task = s_task;
-    if (task >= T) break;
-    // pair of this task
-    int lo = 0, hi = np - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (tbase[mid] <= task) lo = mid; else hi = mid - 1;
+  uint16_t *q16 = reinterpret_cast<uint16_t *>(regs + (uint64_t)w * 2u * smax);
+  // every pass either takes a block or finds a piece used up, so C + Q + 1
+  // passes bound the loop
+  for (uint32_t pass = 0; pass <= C + Q; pass++) {
+    if (piece == Q) {
+      // the piece with the most blocks left (counters read coherently; ties
+      // go to the first piece at or after this workgroup's own)
+      uint64_t key = ~0ull;
+      for (uint32_t i = t; i < Q; i += blockDim.x) {
+        const uint32_t qq = i + r0 < Q ? i + r0 : i + r0 - Q;
+        const uint32_t taken = __hip_atomic_load(&ctr[qq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t cd = plen[qq] - static_blocks(qq, plen[qq], nw);
+        const uint32_t rem = taken < cd ? cd - taken : 0u;
+        const uint64_t kq = ((uint64_t)(~rem) << 32) | i;
+        key = kq < key ? kq : key;
+      }
+      key = wave_min_u64(key);
+      if (lane_id() == 0) s_red[w] = key;
+      __syncthreads();
+      key = s_red[0];
+      for (uint32_t i = 1; i < nw; i++) key = s_red[i] < key ? s_red[i] : key;
+      __syncthreads();  // s_red is read before it is written again
+      if (~(uint32_t)(key >> 32) == 0u) break;
+      const uint32_t i = (uint32_t)key;
+      piece = i + r0 < Q ? i + r0 : i + r0 - Q;
     }
-    const int pair = lo, f = pair / 3, k = pair % 3;
+    const int pair = (int)pgrp[piece];
+    const int f = pair / 3, k = pair % 3;
     const DField &df = D[f];
     const gptr<const DState> st = G(static_cast<const DState *>(df.st));
     if (pair != cur) {
-      __syncthreads();
       const gptr<const uint32_t> gl = G(df.lut) + (uint64_t)k * (2u << kLutBits);
       // eight loads per thread in flight before they are stored
       for (uint32_t i0 = 0; i0 < lut_words; i0 += 8u * blockDim.x) {
@@ -849,25 +890,41 @@ __global__ void d_decode(const DField *__restrict__ D, int nf, const uint32_t *_
     T2.gsyms = G(df.syms) + (uint64_t)k * kNSyms;
     T2.syms_lds = syms_lds;
     T2.maxlen = st->maxlen[k];
-    // the task's run of the group's blocks
-    const uint32_t b0 = tbase[np + 1 + pair], c = tbase[np + 2 + pair] - b0, cut = tbase[2 * np + 2];
-    const uint32_t a = min(c, cut > b0 ? cut - b0 : 0u), nbig = (a + tbig - 1) / tbig, i = task - tbase[pair];
-    const uint32_t first = i < nbig ? i * tbig : a + (i - nbig) * tsmall;
-    const uint32_t cnt = i < nbig ? min(tbig, a - first) : min(tsmall, c - first);
-    // its blocks go to the waves one at a time as they come free, so a wave
-    // that drew short blocks takes more of them
-    uint16_t *q16 = reinterpret_cast<uint16_t *>(regs + (uint64_t)(t / kWave) * 2u * smax);
-    for (;;) {
-      uint32_t j = 0;
-      if (lane_id() == 0) j = atomicAdd(&s_next, 1u);
-      j = __builtin_amdgcn_readfirstlane(j);
-      if (j >= cnt) break;
-      const u32x4 dsc = G(static_cast<const u32x4 *>(df.desc))[st->grp_start[k] + first + j];
+    // the piece's blocks: on the workgroup's first pass over its own piece
+    // the first cs go to the waves in turn (each wave loads its next
+    // descriptor while it decodes a block); the rest, one per wave at a time,
+    // from the piece's counter, which other workgroups share
+    const uint32_t first = (piece - tb[np + 1 + pair]) * L, c = plen[piece];
+    const uint32_t cs = static_blocks(piece, c, nw);
+    const gptr<const u32x4> gdesc = G(static_cast<const u32x4 *>(df.desc)) + st->grp_start[k] + first;
+    if (pass == 0 && blockIdx.x < Q) {
+      uint32_t j = w;
+      u32x4 dsc = j < cs ? gdesc[j] : u32x4{0, 0, 0, 0};
+      while (j < cs) {
+        const uint32_t jn = j + nw;
+        const u32x4 dn = jn < cs ? gdesc[jn] : u32x4{0, 0, 0, 0};
+        int bad = 0;
+        decode_block(df, st, T2, dsc, (uint32_t)k, q16, &bad);
+        if (bad && lane_id() == 0) atomicCAS(&df.st->status, 0, SZNB_ECORRUPT);
+        j = jn;
+        dsc = dn;
+      }
+    }
+    uint32_t *const gctr = ctr + piece;
+    uint32_t j = 0;
+    if (lane_id() == 0) j = atomicAdd(gctr, 1u);
+    j = cs + __builtin_amdgcn_readfirstlane(j);
+    while (j < c) {
+      uint32_t jn = 0;
+      if (lane_id() == 0) jn = atomicAdd(gctr, 1u);
+      const u32x4 dsc = gdesc[j];
       int bad = 0;
       decode_block(df, st, T2, dsc, (uint32_t)k, q16, &bad);
       if (bad && lane_id() == 0) atomicCAS(&df.st->status, 0, SZNB_ECORRUPT);
+      j = cs + __builtin_amdgcn_readfirstlane(jn);
     }
-    __syncthreads();  // every wave is past the task before its counter is reset
+    __syncthreads();  // every wave is done with the piece (and the tables)
+    piece = Q;
   }
 }
 

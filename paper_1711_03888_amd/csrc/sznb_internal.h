@@ -190,6 +190,8 @@ struct alignas(16) DField {
   uint16_t *syms;         // 3 x 65536 canonical symbols
 };
 constexpr int kSlowWords = 128;
+// largest decode grid (workgroups); the decoder's piece tables are sized for it
+constexpr uint32_t kMaxDecodeGrid = 8192;
 
 // decode-table entry: sym | len << 16; flags.  A long entry (a prefix of
 // codes longer than the table's bits) holds the shortest length under the
