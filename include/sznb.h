@@ -95,7 +95,8 @@ int sznb_stream_info(const void *h_hdr, uint64_t hdr_len, uint64_t *n, uint32_t 
 uint64_t sznb_decompress_workspace_bytes(int nf, const uint64_t *h_n);
 
 /* Decompress the stream d_stream[0..stream_len) into d_out[0..n), where n is
- * the field size stored in the stream (checked on the device). */
+ * the field size stored in the stream (checked on the device).  d_stream must
+ * be 8-byte aligned and d_out 16-byte aligned (SZNB_EINVAL otherwise). */
 int sznb_decompress(const void *d_stream, uint64_t stream_len, float *d_out, uint64_t n,
                     void *d_ws, uint64_t ws_bytes, hipStream_t stream);
 

@@ -131,19 +131,38 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
   const uint32_t nsym[3] = {st->nsym[0], st->nsym[1], st->nsym[2]};
   const uint32_t mlen[3] = {st->maxlen[0], st->maxlen[1], st->maxlen[2]};
   const uint32_t cwmax = S * kLMax / 32;
-  const uint32_t per = (nb + kPrepThreads - 1) / kPrepThreads;
-  const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
-  // the block table entries are read kPrepBatch blocks at a time, all loads
-  // of a batch issued before any is used
+  // The block table entries are read kPrepBatch blocks at a time, all loads
+  // of a batch issued before any is used.  Streams start at 8-byte aligned
+  // addresses (the host checks plain streams; a container's sub-streams sit
+  // at multiples of 8 from its aligned start) and the table's sections start
+  // at multiples of 8 of the stream and are padded to 8, so a batch starting
+  // at a block multiple of 8 is read in 8-byte words, each word loaded only
+  // if its first block is in the thread's run (the word then lies inside its
+  // section).
   const gptr<const uint8_t> gin = G(in);
-  const uint64_t ocw = st->off_cwords, one = st->off_nesc, opr = st->off_pred;
+  static_assert(kPrepBatch == 8, "a batch is one 8-byte word of predictor bytes");
+  const uint32_t per = ((nb + kPrepThreads - 1) / kPrepThreads + 7u) & ~7u;
+  const uint32_t lo = min(nb, t * per), hi = min(nb, lo + per);
+  const uint64_t ocw = st->off_cwords, one = st->off_nesc, opr = st->off_pred, opf = st->off_pfirst;
+  auto w64 = [&](uint64_t off) { return *reinterpret_cast<gptr<const uint64_t>>(gin + off); };
   auto batch = [&](uint32_t b0, uint32_t (&cwv)[kPrepBatch], uint32_t (&nev)[kPrepBatch], uint32_t (&kv)[kPrepBatch]) {
+    const bool two = b0 + 4 < hi;
+    const uint64_t c0 = w64(ocw + 2ull * b0), c1 = two ? w64(ocw + 2ull * b0 + 8) : 0ull;
+    const uint64_t n0 = w64(one + 2ull * b0), n1 = two ? w64(one + 2ull * b0 + 8) : 0ull;
+    const uint64_t k8 = policy >= 2 ? w64(opr + b0) : 0ull;
 #pragma unroll
     for (uint32_t j = 0; j < kPrepBatch; j++) {
-      const uint32_t b = min(b0 + j, hi - 1);
-      cwv[j] = rd16(gin, ocw + 2ull * b);
-      nev[j] = rd16(gin, one + 2ull * b);
-      kv[j] = policy >= 2 ? gin[opr + b] : policy;
+      cwv[j] = (uint32_t)((j < 4 ? c0 : c1) >> (16 * (j & 3))) & 0xffffu;
+      nev[j] = (uint32_t)((j < 4 ? n0 : n1) >> (16 * (j & 3))) & 0xffffu;
+      kv[j] = policy >= 2 ? (uint32_t)(k8 >> (8 * j)) & 0xffu : policy;
+    }
+  };
+  auto firsts = [&](uint32_t b0, uint32_t (&p0v)[kPrepBatch]) {
+#pragma unroll
+    for (uint32_t i = 0; i < kPrepBatch / 2; i++) {
+      const uint64_t v = b0 + 2 * i < hi ? w64(opf + 4ull * b0 + 8 * i) : 0ull;
+      p0v[2 * i] = (uint32_t)v;
+      p0v[2 * i + 1] = (uint32_t)(v >> 32);
     }
   };
   uint32_t words = 0, cnt[3] = {0, 0, 0}, bad = 0;
@@ -188,12 +207,10 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
   // each block's descriptor goes to its predictor group's next slot, so a
   // decoding wave reads everything it needs to start a block in one load
   const gptr<u32x4> desc = G(df.desc);
-  const uint64_t opf = st->off_pfirst;
   for (uint32_t b0 = lo; b0 < hi; b0 += kPrepBatch) {
     uint32_t cwv[kPrepBatch], nev[kPrepBatch], kv[kPrepBatch], p0v[kPrepBatch];
     batch(b0, cwv, nev, kv);
-#pragma unroll
-    for (uint32_t j = 0; j < kPrepBatch; j++) p0v[j] = rd32(gin, opf + 4ull * min(b0 + j, hi - 1));
+    firsts(b0, p0v);
 #pragma unroll
     for (uint32_t j = 0; j < kPrepBatch; j++) {
       const uint32_t b = b0 + j;

@@ -197,6 +197,38 @@ def test_batch_equals_single():
         assert np.array_equal(y.cpu().numpy(), oracle.decompress(oracle.compress(x, e, m)))
 
 
+def test_stream_alignment():
+    """Streams start at 8-byte aligned addresses (the decoder reads the block
+    table in 8-byte words): a stream at any other offset is refused with
+    EINVAL, one at offset 8 of a buffer decodes like the oracle, alone and in
+    a batch (block counts that are and are not multiples of 8, one predictor
+    and three)."""
+    print("alignment", flush=True)
+    xs = [_three_predictor_field(), datagen.random_walk(4096 * 9 + 5, seed=11),
+          datagen.cosmology(1 << 15, seed=12)["xx"], datagen.random_walk(4096 * 16, seed=13)]
+    modes = [sznb.PRED_BESTFIT | sznb.EB_REL, sznb.PRED_LV | sznb.EB_REL, sznb.PRED_BESTFIT | sznb.EB_REL,
+             sznb.PRED_LCF | sznb.EB_REL]
+    refs = [oracle.compress(x, 1e-4, m) for x, m in zip(xs, modes)]
+    want = [oracle.decompress(r) for r in refs]
+    for off in range(9):
+        print("offset %d" % off, flush=True)
+        views = []
+        for r in refs:
+            buf = torch.zeros(len(r) + 8, dtype=torch.uint8, device="cuda")
+            buf[off:off + len(r)] = torch.frombuffer(bytearray(r), dtype=torch.uint8).cuda()
+            views.append(buf[off:off + len(r)])
+        if views[0].data_ptr() % 8:
+            with pytest.raises(sznb.SznbError) as e:
+                sznb.decompress(views[0], xs[0].size)
+            assert e.value.code == sznb.EINVAL
+            continue
+        for v, x, w in zip(views, xs, want):
+            assert np.array_equal(sznb.decompress(v, x.size).cpu().numpy().view(np.uint32), w.view(np.uint32)), off
+        outs = sznb.decompress_batch(views, [x.size for x in xs])
+        for o, w in zip(outs, want):
+            assert np.array_equal(o.cpu().numpy().view(np.uint32), w.view(np.uint32)), off
+
+
 def test_workspace_reuse_two_calls():
     print("reuse", flush=True)
     x1 = datagen.random_walk(100000, seed=7)
