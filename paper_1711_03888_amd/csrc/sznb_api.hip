@@ -27,10 +27,10 @@ template <int E> __global__ void k_pack(const CField *, int, const uint64_t *, u
 __global__ void k_final(const CField *, int);
 uint64_t hscratch_bytes_host();
 
-__global__ void d_prep(const DField *, uint32_t);
+__global__ void d_prep(const DField *);
 __global__ void d_heads(const DField *, int, uint32_t *);
 __global__ void d_tables(const DField *);
-__global__ void d_tasks(const DField *, int, uint32_t, uint32_t *, uint32_t *);
+__global__ void d_tasks(const DField *, int, uint32_t, uint32_t, uint32_t *, uint32_t *);
 __global__ void d_const(const DField *, int, const uint32_t *);
 __global__ void d_decode(const DField *, int, uint32_t *, uint32_t, uint32_t, uint32_t);
 
@@ -224,6 +224,17 @@ static int upload(const std::vector<Upload> &ups, hipStream_t s, bool may_stage)
   // pageable source buffers must stay valid until the copies are consumed
   return hipStreamSynchronize(s) == hipSuccess ? SZNB_OK : SZNB_EDEVICE;
 }
+
+// Header read-backs land in a pinned buffer per device (a copy into pageable
+// memory would hold the host until the stream drains), held under the
+// device's own lock from the copy until the values are read.
+constexpr size_t kReadbackBytes = 1u << 16;
+struct Readback {
+  uint32_t *buf = nullptr;
+  bool failed = false;
+  std::mutex mu;
+};
+static Readback g_rb[64];
 
 static int block_log2_of(uint32_t mode) {
   uint32_t b = (mode >> 8) & 15u;
@@ -846,9 +857,18 @@ struct DLaunch {
 // not read back: the launch is laid out for those sizes, the descriptors'
 // stream pointers are left to a kernel (MD containers: md_parse) and the
 // call does not wait for the GPU.
+// The header checks and the decode tables (the first two kernels of every
+// decompression).
+static void launch_front(const DField *D, int nf, hipStream_t stream) {
+  SZNB_LAUNCH("d_prep", d_prep, dim3(nf), dim3(1024), 0, stream, D);
+  SZNB_LAUNCH("d_tables", d_tables, dim3(3 * nf), dim3(kThreads), 0, stream, D);
+}
+
+// With `front`, a call that reads the headers back also enqueues the first
+// two kernels before it waits, and sets *front.
 static int decompress_prepare(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
                               const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream, DLaunch &P,
-                              const uint32_t *assumed = nullptr) {
+                              const uint32_t *assumed = nullptr, bool *front = nullptr) {
   if (nf <= 0 || !d_ws) return SZNB_EINVAL;
   DevInfo *dv;
   int rc = dev_init(&dv);
@@ -883,20 +903,48 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
     smax = assumed[0];
     nsym_max = assumed[1];
   } else {
-    if (hipMemcpyAsync(ws + L.fields, hf.data(), sizeof(DField) * nf, hipMemcpyHostToDevice, stream) != hipSuccess)
-      return SZNB_EDEVICE;
+    rc = upload({{ws + L.fields, hf.data(), sizeof(DField) * nf}}, stream, true);
+    if (rc) return rc;
     const DField *D = reinterpret_cast<const DField *>(ws + L.fields);
     SZNB_LAUNCH("d_heads", d_heads, dim3((nf + 255) / 256), dim3(256), 0, stream, D, nf,
                 reinterpret_cast<uint32_t *>(ws + L.heads));
-    std::vector<uint32_t> heads(4ull * nf);
-    if (hipMemcpyAsync(heads.data(), ws + L.heads, 16ull * nf, hipMemcpyDeviceToHost, stream) != hipSuccess)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SZNB_EDEVICE;
+    Readback &rb = g_rb[dev];
+    std::unique_lock<std::mutex> rlk(rb.mu, std::defer_lock);
+    std::vector<uint32_t> hv;
+    uint32_t *heads = nullptr;
+    if (16ull * nf <= kReadbackBytes) {
+      rlk.lock();
+      if (!rb.buf && !rb.failed &&
+          hipHostMalloc(reinterpret_cast<void **>(&rb.buf), kReadbackBytes, hipHostMallocDefault) != hipSuccess) {
+        rb.buf = nullptr;
+        rb.failed = true;
+      }
+      if (rb.buf) heads = rb.buf; else rlk.unlock();
+    }
+    if (!heads) {
+      hv.resize(4ull * nf);
+      heads = hv.data();
+    }
+    if (hipMemcpyAsync(heads, ws + L.heads, 16ull * nf, hipMemcpyDeviceToHost, stream) != hipSuccess)
       return SZNB_EDEVICE;
-    // the header read-back: the launch layout depends on the block and
-    // codebook sizes (the pageable descriptor copy is consumed by then)
-    if (hipStreamSynchronize(stream) != hipSuccess) return SZNB_EDEVICE;
+    hipEvent_t got;
+    if (hipEventCreateWithFlags(&got, hipEventDisableTiming) != hipSuccess) return SZNB_EDEVICE;
+    bool ok = hipEventRecord(got, stream) == hipSuccess;
+    // header checks and decode tables need no launch layout: they run on
+    // the device while the host waits for the header read-back (the launch
+    // layout depends on the block and codebook sizes)
+    if (ok && front) {
+      launch_front(D, nf, stream);
+      *front = true;
+    }
+    ok = ok && hipEventSynchronize(got) == hipSuccess;
+    hipEventDestroy(got);
+    if (!ok) return SZNB_EDEVICE;
     for (int f = 0; f < nf; f++) {
       const uint32_t S = heads[4 * f];
-      if (S >= 1024 && S <= 16384 && !(S & (S - 1)) && S > smax) smax = S;
+      if (S >= kMinBlock && S <= kMaxBlock && !(S & (S - 1)) && S > smax) smax = S;
       for (int k = 0; k < 3; k++) {
         const uint32_t ns = heads[4 * f + 1 + k];
         if (ns <= (uint32_t)kNSyms && ns > nsym_max) nsym_max = ns;
@@ -942,14 +990,15 @@ static int decompress_prepare(int nf, const void *const *streams, const uint64_t
 }
 
 // Kernels only (capturable): streams whose block size exceeds the planned
-// one are reported corrupt rather than decoded.
-static int decompress_run(const DLaunch &P, hipStream_t stream) {
+// one are reported corrupt rather than decoded.  front_done: the first two
+// kernels are already enqueued.
+static int decompress_run(const DLaunch &P, hipStream_t stream, bool front_done = false) {
   const DField *D = reinterpret_cast<const DField *>(P.ws + P.L.fields);
   uint32_t *tbase = reinterpret_cast<uint32_t *>(P.ws + P.L.tbase);
-  SZNB_LAUNCH("d_prep", d_prep, dim3(P.nf), dim3(1024), 0, stream, D, P.smax);
-  SZNB_LAUNCH("d_tables", d_tables, dim3(3 * P.nf), dim3(kThreads), 0, stream, D);
+  if (!front_done) launch_front(D, P.nf, stream);
   uint32_t *nconst = &reinterpret_cast<GCtl *>(P.ws + P.L.gctl)->pad[0];
-  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, (uint32_t)P.grid, tbase, nconst);
+  SZNB_LAUNCH("d_tasks", d_tasks, dim3(1), dim3(kThreads), 0, stream, D, P.nf, (uint32_t)P.grid, P.smax, tbase,
+              nconst);
   SZNB_LAUNCH("d_const", d_const, dim3(256), dim3(kThreads), 0, stream, D, P.nf, nconst);
   SZNB_LAUNCH("d_decode", d_decode, dim3(P.grid), dim3(kWave * P.dw), P.lds, stream, D, P.nf, tbase, P.smax,
               P.symcap, P.lut_words);
@@ -959,9 +1008,10 @@ static int decompress_run(const DLaunch &P, hipStream_t stream) {
 static int decompress_impl(int nf, const void *const *streams, const uint64_t *lens, float *const *outs,
                            const uint64_t *n, void *d_ws, uint64_t ws_bytes, hipStream_t stream) {
   DLaunch P;
-  int rc = decompress_prepare(nf, streams, lens, outs, n, d_ws, ws_bytes, stream, P);
+  bool front = false;
+  int rc = decompress_prepare(nf, streams, lens, outs, n, d_ws, ws_bytes, stream, P, nullptr, &front);
   if (rc) return rc;
-  return decompress_run(P, stream);
+  return decompress_run(P, stream, front);
 }
 
 static int dplan_run(void *dplan, hipStream_t stream) {

@@ -46,7 +46,7 @@ __global__ void d_heads(const DField *__restrict__ D, int nf, uint32_t *heads) {
 
 constexpr int kPrepThreads = 1024;
 constexpr uint32_t kPrepBatch = 8;
-__global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict__ D, uint32_t smax) {
+__global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict__ D) {
   const DField &df = D[blockIdx.x];
   DState *st = df.st;
   const uint8_t *in = df.in;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kPrepThreads) void d_prep(const DField *__restrict_
       S = rd32(hb, H_S);
       nb = rd32(hb, H_NB);
       total = rd64(hb, H_TOTAL);
-      if (policy > 3 || n != df.n || total > df.in_len || S < 1024 || S > smax || (S & (S - 1))) bad = 1;
+      if (policy > 3 || n != df.n || total > df.in_len || S < kMinBlock || S > kMaxBlock || (S & (S - 1))) bad = 1;
     }
     st->policy = policy; st->S = S; st->n = n;
     st->mn = __uint_as_float(bad ? 0u : rd32(hb, H_MN));
@@ -401,7 +401,7 @@ __device__ inline uint32_t wg_excl_scan(uint32_t v, uint32_t *s_tot, uint32_t &t
 }
 
 __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D, int nf, uint32_t grid,
-                                                    uint32_t *tb, uint32_t *nconst) {
+                                                    uint32_t smax, uint32_t *tb, uint32_t *nconst) {
   __shared__ uint32_t s_tot[kThreads / kWave];
   __shared__ uint32_t s_const;
   const int t = threadIdx.x;
@@ -411,17 +411,19 @@ __global__ __launch_bounds__(kThreads) void d_tasks(const DField *__restrict__ D
   const int per = (np + kThreads - 1) / kThreads;
   if (t == 0) s_const = 0;
   __syncthreads();
-  auto blocks = [&](int p) -> uint32_t {
-    const DState *st = D[p / 3].st;
-    return st->status == 0 && !st->is_const ? st->grp_count[p % 3] : 0u;
-  };
+  // a stream whose blocks are longer than the decoder's code regions (laid
+  // out for the largest block size the host planned for) is reported
+  // corrupt and decodes nothing
+  auto fits = [&](const DState *st) { return st->status == 0 && !st->is_const && st->S <= smax; };
+  auto blocks = [&](int p) -> uint32_t { return fits(D[p / 3].st) ? D[p / 3].st->grp_count[p % 3] : 0u; };
   uint32_t loc = 0, ncon = 0;
   for (int j = 0; j < per; j++) {
     const int p = t * per + j;
     if (p < np) {
       loc += blocks(p);
-      const DState *st = D[p / 3].st;
+      DState *st = D[p / 3].st;
       if (p % 3 == 0 && st->status == 0 && st->is_const) ncon++;
+      if (p % 3 == 0 && st->status == 0 && !st->is_const && st->S > smax) st->status = SZNB_ECORRUPT;
     }
   }
   if (ncon) atomicAdd(&s_const, ncon);

@@ -190,6 +190,8 @@ struct alignas(16) DField {
   uint16_t *syms;         // 3 x 65536 canonical symbols
 };
 constexpr int kSlowWords = 128;
+// block sizes of the stream format: powers of two from 2^10 to 2^14 values
+constexpr uint32_t kMinBlock = 1024, kMaxBlock = 16384;
 // largest decode grid (workgroups); the decoder's piece tables are sized for it
 constexpr uint32_t kMaxDecodeGrid = 8192;
 
