@@ -264,10 +264,28 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
     if (t == 0) st->status = SZNB_ECORRUPT;
     return;
   }
-  uint16_t *syms = df.syms + (uint64_t)k * kNSyms;
+  // the canonical symbols (ns 16-bit words at so, a multiple of 4 in an
+  // 8-byte aligned stream; the book is padded to 8 bytes) go to the
+  // workspace two at a time, four loads per thread in flight.  The first
+  // level below reads the few it needs straight from the stream, so it does
+  // not wait for this copy.
   const uint64_t so = bo + 4ull * ml;
-  for (uint32_t i = t; i < ns; i += kThreads) syms[i] = rd16(in, so + 2ull * i);
-  __syncthreads();
+  const gptr<const uint32_t> sw = reinterpret_cast<gptr<const uint32_t>>(G(in) + so);
+  const gptr<uint32_t> symw = reinterpret_cast<gptr<uint32_t>>(G(df.syms) + (uint64_t)k * kNSyms);
+  const uint32_t npair = (ns + 1) / 2;
+  for (uint32_t i0 = 0; i0 < npair; i0 += 4u * kThreads) {
+    uint32_t a[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + (uint32_t)u * kThreads + t;
+      a[u] = i < npair ? sw[i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const uint32_t i = i0 + (uint32_t)u * kThreads + t;
+      if (i < npair) symw[i] = a[u];
+    }
+  }
   // first code of every 12-bit window: its symbol and length, then how many
   // whole codes the window holds and their total length (bits 24-27 and
   // 28-31: the counting pass steps over all of them at once)
@@ -292,8 +310,8 @@ __global__ __launch_bounds__(kThreads) void d_tables(const DField *__restrict__ 
       ent = kLutLong | (len << 16);
       if (ll == len) ent |= kLutOne | (s_base[len] - s_first[len] + (e << (len - kLutBits)));
     } else {
-      const uint32_t code = (uint32_t)(win >> (32 - len));
-      ent = (uint32_t)syms[s_base[len] + (code - s_first[len])] | (len << 16);
+      const uint32_t code = (uint32_t)(win >> (32 - len)), si = s_base[len] + (code - s_first[len]);
+      ent = ((sw[si >> 1] >> (16u * (si & 1u))) & 0xffffu) | (len << 16);
     }
     ents[j] = ent;
     s_len[e] = (uint8_t)((ent & (kLutInvalid | kLutLong)) ? 0u : len);
