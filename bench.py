@@ -50,9 +50,13 @@ def measured_traffic(kernel, tag):
     from paper_1711_03888_amd.profile_summary import source_hash
     with open(path) as f:
         t = json.load(f)
-    if t.get("source_sha256") != source_hash() or kernel not in t.get("kernels", {}):
+    if t.get("source_sha256") != source_hash():
         return None
-    return round(t["kernels"][kernel]["bytes"])
+    # the traces name template kernels with their arguments (k_pack<16>)
+    keys = [k for k in t.get("kernels", {}) if k == kernel or k.startswith(kernel + "<")]
+    if len(keys) != 1:
+        return None
+    return round(t["kernels"][keys[0]]["bytes"])
 
 
 def md_modes(dev, eb, reps):
