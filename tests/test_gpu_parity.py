@@ -229,6 +229,29 @@ def test_stream_alignment():
             assert np.array_equal(o.cpu().numpy().view(np.uint32), w.view(np.uint32)), off
 
 
+def test_decompress_many_small_streams():
+    """More (stream, predictor) groups than decode workgroups: 700 streams of
+    1 to 9 blocks (ragged ends, three policies, some constant) in one batch,
+    so the decoder has pieces without a workgroup of their own and every
+    workgroup moves between groups; every output equals the oracle's."""
+    print("many streams", flush=True)
+    rng = np.random.default_rng(33)
+    xs, modes, ebs = [], [], []
+    for i in range(700):
+        n = int(rng.integers(1, 9)) * 4096 + int(rng.integers(0, 4096))
+        x = np.full(n, 2.5, np.float32) if i % 97 == 0 else datagen.random_walk(n, seed=1000 + i)
+        xs.append(x)
+        modes.append([sznb.PRED_LV, sznb.PRED_LCF, sznb.PRED_BESTFIT][i % 3] | sznb.EB_REL)
+        ebs.append([1e-3, 1e-4, 3e-4][i % 3])
+    streams = sznb.compress_batch([torch.from_numpy(x).cuda() for x in xs], ebs, modes)
+    refs = [oracle.compress(x, e, m) for x, e, m in zip(xs, ebs, modes)]
+    for i, (s_, r) in enumerate(zip(streams, refs)):
+        assert bytes(s_.cpu().numpy()) == r, i
+    outs = sznb.decompress_batch(streams, [x.size for x in xs])
+    for i, (o, r) in enumerate(zip(outs, refs)):
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), oracle.decompress(r).view(np.uint32)), i
+
+
 def test_workspace_reuse_two_calls():
     print("reuse", flush=True)
     x1 = datagen.random_walk(100000, seed=7)
