@@ -817,14 +817,6 @@ __device__ __forceinline__ void decode_block(const DField &df, gptr<const DState
   __builtin_amdgcn_wave_barrier();
 }
 
-// Workgroup g of G starts on piece g: its waves take three quarters of the
-// piece's blocks in turn and the rest one at a time from the piece's
-// counter, so a wave that drew short blocks takes more, and the workgroup
-// meets at a barrier only when the piece is used up.  It then helps with the
-// piece with the most counter-served blocks left, until none has any.  Dynamic LDS: lut (4096 words), lut2 (4096 words when some
-// codebook is small enough to use it) | first, base (32 words each) | limit
-// (32 u64) | symbols (symcap u16, when they fit) | dw code regions of 2 smax
-// bytes.
 // Blocks of piece q (of c blocks) that its own workgroup decodes without the
 // counter: three quarters, in whole turns of the nw waves.  Pieces past the
 // grid have no workgroup of their own and are all counter-served.
@@ -832,6 +824,14 @@ __device__ inline uint32_t static_blocks(uint32_t q, uint32_t c, uint32_t nw) {
   return q < gridDim.x ? c * 3u / 4u / nw * nw : 0u;
 }
 
+// Workgroup g of G starts on piece g: its waves take three quarters of the
+// piece's blocks in turn and the rest one at a time from the piece's
+// counter, so a wave that drew short blocks takes more, and the workgroup
+// meets at a barrier only when the piece is used up.  It then helps with the
+// piece with the most counter-served blocks left, until none has any.
+// Dynamic LDS: lut (4096 words), lut2 (4096 words when some codebook is
+// small enough to use it) | first, base (32 words each) | limit (32 u64) |
+// symbols (symcap u16, when they fit) | dw code regions of 2 smax bytes.
 __global__ void d_decode(const DField *__restrict__ D, int nf, uint32_t *tb, uint32_t smax, uint32_t symcap,
                          uint32_t lut_words) {
   extern __shared__ __align__(16) uint8_t smem[];
