@@ -276,6 +276,11 @@ int sznb_md_decompress(const void *d_in, uint64_t in_len, int nf, uint64_t n, fl
  * dropped). */
 int sznb_profile(int enable);
 int sznb_profile_summary(int max_kernels, char *names, double *total_ms, int *count);
+/* Restricts the bracketing to the kernels named in `names` (comma-separated,
+ * as sznb_profile_summary names them); NULL or "" brackets every kernel.
+ * Each bracket costs the stream a few microseconds between kernels, so a
+ * measurement that needs only some kernels' durations names them. */
+int sznb_profile_kernels(const char *names);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,19 @@ static std::vector<ProfRec> g_prof;
 static std::vector<hipEvent_t> g_evpool;
 static size_t g_evnext = 0;
 static bool g_prof_on = false;
+static std::string g_prof_only;  // comma-separated kernel names to bracket; empty: every kernel
+
+static bool prof_wanted(const char *name) {
+  if (g_prof_only.empty()) return true;
+  const size_t n = std::strlen(name);
+  for (size_t p = 0; p <= g_prof_only.size();) {
+    size_t q = g_prof_only.find(',', p);
+    if (q == std::string::npos) q = g_prof_only.size();
+    if (q - p == n && g_prof_only.compare(p, n, name) == 0) return true;
+    p = q + 1;
+  }
+  return false;
+}
 
 static hipEvent_t prof_event() {
   if (g_evnext == g_evpool.size()) {
@@ -92,7 +105,7 @@ struct ProfScope {
   const char *name;
   hipStream_t s;
   ProfScope(const char *n, hipStream_t st) : name(n), s(st) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || !prof_wanted(n)) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     hipEvent_t a = prof_event();
@@ -1507,6 +1520,11 @@ int sznb_profile(int enable) {
     g_evnext = 0;
   }
   g_prof_on = enable != 0;
+  return SZNB_OK;
+}
+
+int sznb_profile_kernels(const char *names) {
+  g_prof_only = names ? names : "";
   return SZNB_OK;
 }
 

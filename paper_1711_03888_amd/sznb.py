@@ -250,8 +250,12 @@ def decompress(s: torch.Tensor, n: int | None = None, **kw) -> torch.Tensor:
     return decompress_batch([s], None if n is None else [n], **kw)[0]
 
 
-def profile(enable: bool) -> None:
-    """Bracket every later kernel launch with HIP events (or stop)."""
+def profile(enable: bool, only=None) -> None:
+    """Bracket every later kernel launch with HIP events (or stop); `only`:
+    the kernel names to bracket (each bracket costs the stream a few
+    microseconds between kernels), None for every kernel."""
+    if enable:
+        lib().sznb_profile_kernels(ctypes.c_char_p(",".join(only).encode() if only else None))
     lib().sznb_profile(1 if enable else 0)
 
 
